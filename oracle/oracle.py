@@ -1,0 +1,392 @@
+"""Test infrastructure only: the plain FP64 CPU oracle of the kernelised-periodogram period search.
+
+Only ``tests/``, the smoke check and the benchmark's CPU-baseline leg may import this module.  It
+shares no code with the HIP library (``paper_1412_1840_amd``) and never imports it.
+
+Citations are to Protopapas et al., "A novel, fully automated pipeline for period estimation in
+the EROS 2 data set" (arXiv:1412.1840).  The pair sums are in ``qmi_oracle.c``; this module holds
+the kernel-width rules, the score formulas, the coarse-to-fine search and the discriminator, each
+written plainly in FP64 from its definition.
+
+Readings of points the paper leaves open (kept identical in the HIP library, which implements them
+separately):
+
+* the score searched by default is the Cauchy-Schwarz quadratic mutual information built from the
+  same pair sums as the CKP (Sec. 3): QMI = ln V_J + ln V_M - 2 ln V_C;
+* sums include the diagonal i = j, as the CKP definition (Sec. 3) is written;
+* sigma_y defaults to Silverman's rule 0.9 min(s, IQR/1.34) N^(-1/5) with s on N-1 and
+  linear-interpolation quartiles; IQR = 0 falls back to s; s = 0 is degenerate.  The paper's own
+  rule sigma_y = median(error bars) (Sec. 3) is the alternative;
+* peaks of the coarse periodogram are its local maxima (q_k > q_{k-1} and q_k >= q_{k+1}; the first
+  point needs q_0 >= q_1, the last q_{F-1} > q_{F-2}), ranked by value with ties to lower k;
+* each kept peak k is refined on n_fine evenly spaced points of [f_{k-1}, f_{k+1}] (clamped to the
+  grid's ends); the best is the highest refined score, ties to the lower frequency, then the lower
+  peak rank;
+* pSNR = 0.7413 iqr(y) / (alpha median(e)) with alpha = 1 (Sec. 5.2); the eight SNR bins of the
+  threshold table of Sec. 4.1 are half-open [a, b); a curve is periodic iff score > th(bin).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+SIGMA_SILVERMAN = -1.0
+SIGMA_MEDIAN_ERR = -2.0
+SCORE_QMI = 0
+SCORE_NCKP = 1
+
+SNR_EDGES = (0.0, 1.5, 2.0, 2.5, 3.5, 5.0, 10.0, 20.0, math.inf)
+UNDECIDED = 255
+
+
+class Degenerate(ValueError):
+    """The kernel-width rule gives zero (e.g. all magnitudes equal)."""
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(HERE, "liboracle.so")
+        src = os.path.join(HERE, "qmi_oracle.c")
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(src):
+            from . import build_oracle  # noqa: WPS433  (builds the checker, test-side only)
+            build_oracle.build()
+        lib = ctypes.CDLL(path)
+        P = ctypes.POINTER
+        lib.oracle_batch_ips.argtypes = [ctypes.c_int64, P(ctypes.c_int64), P(ctypes.c_double),
+                                         P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_double),
+                                         P(ctypes.c_int64), P(ctypes.c_double), ctypes.c_int,
+                                         P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_double),
+                                         P(ctypes.c_double), ctypes.c_int]
+        lib.oracle_batch_ips.restype = ctypes.c_int
+        lib.oracle_threads.argtypes = [ctypes.c_int]
+        lib.oracle_threads.restype = ctypes.c_int
+        _LIB = lib
+    return _LIB
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def threads(n_threads: int = 0) -> int:
+    return int(_lib().oracle_threads(int(n_threads)))
+
+
+# ------------------------------------------------------------------------------------------
+# Order statistics (written out; linear interpolation between order statistics)
+# ------------------------------------------------------------------------------------------
+
+def quantile(x: np.ndarray, p: float) -> float:
+    """Quantile by linear interpolation between the order statistics at position (N-1) p."""
+    s = sorted(float(v) for v in x)
+    n = len(s)
+    h = (n - 1) * p
+    lo = int(math.floor(h))
+    hi = min(lo + 1, n - 1)
+    return s[lo] + (h - lo) * (s[hi] - s[lo])
+
+
+def median(x: np.ndarray) -> float:
+    s = sorted(float(v) for v in x)
+    n = len(s)
+    if n % 2:
+        return s[n // 2]
+    return 0.5 * (s[n // 2 - 1] + s[n // 2])
+
+
+def iqr(x: np.ndarray) -> float:
+    return quantile(x, 0.75) - quantile(x, 0.25)
+
+
+# ------------------------------------------------------------------------------------------
+# Kernel widths (Sec. 3: sigma_y from the error bars; sigma_t a free parameter in [0.1, 0.6])
+# ------------------------------------------------------------------------------------------
+
+def silverman_sigma(y: np.ndarray) -> float:
+    n = len(y)
+    mean = sum(float(v) for v in y) / n
+    s = math.sqrt(sum((float(v) - mean) ** 2 for v in y) / (n - 1)) if n > 1 else 0.0
+    if s == 0.0:
+        raise Degenerate("Silverman's rule: zero sample deviation")
+    q = iqr(y)
+    spread = s if q == 0.0 else min(s, q / 1.34)
+    return 0.9 * spread * n ** (-0.2)
+
+
+def sigma_y_of(y: np.ndarray, e: Optional[np.ndarray], rule: float) -> float:
+    """sigma_y > 0 explicit; -1 Silverman; -2 median of the error bars (Sec. 3)."""
+    if rule > 0:
+        return float(rule)
+    if rule == SIGMA_SILVERMAN:
+        return silverman_sigma(y)
+    if rule == SIGMA_MEDIAN_ERR:
+        if e is None:
+            raise ValueError("median-error-bar rule needs error bars")
+        m = median(e)
+        if not m > 0:
+            raise Degenerate("median error bar is not positive")
+        return m
+    raise ValueError("unknown sigma_y rule %r" % rule)
+
+
+# ------------------------------------------------------------------------------------------
+# Information potentials and scores
+# ------------------------------------------------------------------------------------------
+
+@dataclass
+class IPs:
+    vj: np.ndarray  # joint information potential V_J(f)
+    ipt: np.ndarray  # marginal information potential of the warped times IP_t(f)
+    vc: np.ndarray  # cross information potential V_C(f)
+    ipy: float  # marginal information potential of the magnitudes (Sec. 3)
+    n: int
+    sigma_t: float
+    sigma_y: float
+
+
+def information_potentials(t, y, sigma_t: float, sigma_y: float, freqs, mode: int = 1,
+                           n_threads: int = 0) -> IPs:
+    """V_J, IP_t, V_C at each frequency and IP_y, all pairs in FP64 (C part, ``mode`` 0 = plain
+    double loop, 1 = i<j doubled plus the closed-form diagonal)."""
+    res = batch_information_potentials([np.asarray(t, np.float64)], [np.asarray(y, np.float64)],
+                                       [sigma_t], [sigma_y], [np.asarray(freqs, np.float64)],
+                                       mode, n_threads)
+    return res[0]
+
+
+def batch_information_potentials(ts: Sequence[np.ndarray], ys: Sequence[np.ndarray],
+                                 sigma_t: Sequence[float], sigma_y: Sequence[float],
+                                 freqs: Sequence[np.ndarray], mode: int = 1,
+                                 n_threads: int = 0) -> List[IPs]:
+    nc = len(ts)
+    offsets = np.zeros(nc + 1, np.int64)
+    offsets[1:] = np.cumsum([len(x) for x in ts])
+    foff = np.zeros(nc + 1, np.int64)
+    foff[1:] = np.cumsum([len(f) for f in freqs])
+    t = np.ascontiguousarray(np.concatenate(ts) if nc else np.zeros(0), np.float64)
+    y = np.ascontiguousarray(np.concatenate(ys) if nc else np.zeros(0), np.float64)
+    f = np.ascontiguousarray(np.concatenate(freqs) if nc else np.zeros(0), np.float64)
+    st = np.ascontiguousarray(sigma_t, np.float64)
+    sy = np.ascontiguousarray(sigma_y, np.float64)
+    vj = np.zeros(len(f))
+    ipt = np.zeros(len(f))
+    vc = np.zeros(len(f))
+    ipy = np.zeros(nc)
+    D = ctypes.c_double
+    rc = _lib().oracle_batch_ips(nc, _ptr(offsets, ctypes.c_int64), _ptr(t, D), _ptr(y, D),
+                                 _ptr(st, D), _ptr(sy, D), _ptr(foff, ctypes.c_int64), _ptr(f, D),
+                                 int(mode), _ptr(vj, D), _ptr(ipt, D), _ptr(vc, D), _ptr(ipy, D),
+                                 int(n_threads))
+    if rc != 0:
+        raise ValueError("oracle_batch_ips failed (%d)" % rc)
+    out = []
+    for c in range(nc):
+        a, b = foff[c], foff[c + 1]
+        out.append(IPs(vj[a:b].copy(), ipt[a:b].copy(), vc[a:b].copy(), float(ipy[c]),
+                       len(ts[c]), float(st[c]), float(sy[c])))
+    return out
+
+
+def qmi(ips: IPs) -> np.ndarray:
+    """Cauchy-Schwarz QMI = ln(V_J V_M / V_C^2), V_M = IP_y IP_t, evaluated in FP64."""
+    vm = ips.ipy * ips.ipt
+    return np.log(ips.vj) + np.log(vm) - 2.0 * np.log(ips.vc)
+
+
+def ckp(ips: IPs) -> np.ndarray:
+    """CKP (Sec. 3) = (1/N^2) sum_ij (G_sy(dy) - IP_y) G^P = V_J - IP_y IP_t."""
+    return ips.vj - ips.ipy * ips.ipt
+
+
+def nckp(ips: IPs) -> np.ndarray:
+    """Normalised CKP (Sec. 3): sqrt(N sigma_t) / IP_y * CKP."""
+    return math.sqrt(ips.n * ips.sigma_t) / ips.ipy * ckp(ips)
+
+
+def score_of(ips: IPs, score: int) -> np.ndarray:
+    return qmi(ips) if score == SCORE_QMI else nckp(ips)
+
+
+# ------------------------------------------------------------------------------------------
+# Coarse-to-fine search (the CKP is maximised over frequency for fixed widths, Sec. 3; trial
+# frequencies are the highest local maxima of a spectrum, as in the bands method of Sec. 3.1)
+# ------------------------------------------------------------------------------------------
+
+def linear_grid(f_lo: float, f_hi: float, n: int) -> np.ndarray:
+    """n evenly spaced points, f_k = f_lo + k * ((f_hi - f_lo) / (n - 1)), from k (no running sum)."""
+    if n == 1:
+        return np.array([f_lo])
+    step = (f_hi - f_lo) / (n - 1)
+    return np.array([f_lo + float(k) * step for k in range(n)])
+
+
+def local_maxima(q: np.ndarray) -> List[int]:
+    F = len(q)
+    if F == 1:
+        return [0] if q[0] == q[0] else []
+    peaks = []
+    for k in range(F):
+        if k == 0:
+            ok = q[0] >= q[1]
+        elif k == F - 1:
+            ok = q[k] > q[k - 1]
+        else:
+            ok = q[k] > q[k - 1] and q[k] >= q[k + 1]
+        if ok:
+            peaks.append(k)
+    return peaks
+
+
+def top_peaks(q: np.ndarray, top_k: int) -> List[int]:
+    peaks = local_maxima(q)
+    peaks.sort(key=lambda k: (-q[k], k))
+    return peaks[:top_k]
+
+
+def fine_window(coarse: np.ndarray, k: int) -> Tuple[float, float]:
+    """[f_{k-1}, f_{k+1}]; at the ends of the grid [f_0, f_1] and [f_{F-2}, f_{F-1}]."""
+    F = len(coarse)
+    if F == 1:
+        return float(coarse[0]), float(coarse[0])
+    if k == 0:
+        return float(coarse[0]), float(coarse[1])
+    if k == F - 1:
+        return float(coarse[F - 2]), float(coarse[F - 1])
+    return float(coarse[k - 1]), float(coarse[k + 1])
+
+
+@dataclass
+class SearchResult:
+    f_best: float
+    score: float  # the searched score at f_best
+    qmi: float
+    nckp: float
+    coarse_index: int  # k of the refined peak that holds the best (or the coarse argmax)
+    peak_rank: int
+    fine_index: int
+    coarse_argmax: int
+    n_peaks: int
+    sigma_y: float
+    ipy: float
+    coarse_scores: np.ndarray
+    fine_scores: Optional[np.ndarray]  # [n_peaks, n_fine]
+
+
+def best_period(t, y, e, sigma_t: float, sigma_y_rule: float, f_min: float, f_max: float,
+                n_coarse: int, top_k: int, n_fine: int, score: int = SCORE_QMI,
+                mode: int = 1, n_threads: int = 0) -> SearchResult:
+    t = np.asarray(t, np.float64)
+    y = np.asarray(y, np.float64)
+    sy = sigma_y_of(y, None if e is None else np.asarray(e, np.float64), sigma_y_rule)
+    grid = linear_grid(f_min, f_max, n_coarse)
+    ips = information_potentials(t, y, sigma_t, sy, grid, mode, n_threads)
+    q = score_of(ips, score)
+    q_all = (qmi(ips), nckp(ips))
+    arg = int(np.argmax(q)) if not np.all(np.isnan(q)) else 0  # np.argmax: first maximum
+    if top_k <= 0 or n_fine <= 0:
+        return SearchResult(float(grid[arg]), float(q[arg]), float(q_all[0][arg]),
+                            float(q_all[1][arg]), arg, -1, -1, arg, 0, sy, ips.ipy, q, None)
+    peaks = top_peaks(q, top_k)
+    if not peaks:
+        return SearchResult(float(grid[arg]), float(q[arg]), float(q_all[0][arg]),
+                            float(q_all[1][arg]), arg, -1, -1, arg, 0, sy, ips.ipy, q, None)
+    fine_f = [linear_grid(*fine_window(grid, k), n_fine) for k in peaks]
+    fips = information_potentials(t, y, sigma_t, sy, np.concatenate(fine_f), mode, n_threads)
+    fq = score_of(fips, score).reshape(len(peaks), n_fine)
+    fq_all = (qmi(fips).reshape(len(peaks), n_fine), nckp(fips).reshape(len(peaks), n_fine))
+    best = None
+    for rank, k in enumerate(peaks):
+        for m in range(n_fine):
+            key = (-fq[rank, m], fine_f[rank][m], rank, m)
+            if not (fq[rank, m] == fq[rank, m]):
+                continue
+            if best is None or key < best[0]:
+                best = (key, rank, m)
+    if best is None:
+        return SearchResult(float(grid[arg]), float(q[arg]), float(q_all[0][arg]),
+                            float(q_all[1][arg]), arg, -1, -1, arg, len(peaks), sy, ips.ipy, q, fq)
+    _, rank, m = best
+    return SearchResult(float(fine_f[rank][m]), float(fq[rank, m]), float(fq_all[0][rank, m]),
+                        float(fq_all[1][rank, m]), peaks[rank], rank, m, arg, len(peaks), sy,
+                        ips.ipy, q, fq)
+
+
+# ------------------------------------------------------------------------------------------
+# Discrimination (Sec. 4.1 threshold procedure and decision rule; Sec. 5.2 pSNR; Sec. 3.2 scores)
+# ------------------------------------------------------------------------------------------
+
+def psnr(y: np.ndarray, e: np.ndarray, alpha: float = 1.0) -> float:
+    """pseudo signal-to-noise ratio 0.7413 iqr(y) / (alpha med(e)) (Sec. 5.2)."""
+    return 0.7413 * iqr(y) / (alpha * median(e))
+
+
+def snr_bin(p: float, edges: Sequence[float] = SNR_EDGES) -> int:
+    """Index b with edges[b] <= p < edges[b+1]; -1 when p is outside every bin or NaN."""
+    for b in range(len(edges) - 1):
+        if edges[b] <= p < edges[b + 1]:
+            return b
+    return -1
+
+
+def discriminate(score: float, p: float, th: Sequence[float],
+                 edges: Sequence[float] = SNR_EDGES) -> int:
+    """1 if score > th(bin of p) (strict, Sec. 4.1), 0 if not, UNDECIDED without a bin/score."""
+    b = snr_bin(p, edges)
+    if b < 0 or not (score == score):
+        return UNDECIDED
+    return 1 if score > th[b] else 0
+
+
+def f_beta(p: float, r: float, beta: float = 1.0) -> float:
+    """F-score (Sec. 3.2) with the standard beta^2 p + r denominator (identical for beta = 1)."""
+    den = beta * beta * p + r
+    return 0.0 if den == 0 else (1.0 + beta * beta) * p * r / den
+
+
+def precision_recall(pred: Sequence[bool], truth: Sequence[bool]) -> Tuple[float, float]:
+    tp = sum(1 for a, b in zip(pred, truth) if a and b)
+    fp = sum(1 for a, b in zip(pred, truth) if a and not b)
+    fn = sum(1 for a, b in zip(pred, truth) if (not a) and b)
+    p = tp / (tp + fp) if tp + fp else 0.0
+    r = tp / (tp + fn) if tp + fn else 0.0
+    return p, r
+
+
+def calibrate_thresholds(scores: Sequence[float], psnrs: Sequence[float],
+                         truth: Sequence[bool], edges: Sequence[float] = SNR_EDGES,
+                         n_points: int = 5000) -> Dict[str, list]:
+    """Per SNR bin, the F1-maximising threshold over n_points evenly spaced values in
+    [min score, max score] of that bin (Sec. 4.1).  Ties go to the lowest threshold.  A bin with no
+    periodic member gets th = max score (nothing above it), an empty bin th = +inf."""
+    nb = len(edges) - 1
+    th, fs, ps, rs = [], [], [], []
+    for b in range(nb):
+        idx = [i for i in range(len(scores)) if snr_bin(psnrs[i], edges) == b and
+               scores[i] == scores[i]]
+        if not idx:
+            th.append(math.inf); fs.append(0.0); ps.append(0.0); rs.append(0.0)
+            continue
+        s = [float(scores[i]) for i in idx]
+        lab = [bool(truth[i]) for i in idx]
+        if not any(lab):
+            th.append(max(s)); fs.append(0.0); ps.append(0.0); rs.append(0.0)
+            continue
+        cand = linear_grid(min(s), max(s), n_points) if n_points > 1 else np.array([min(s)])
+        best = None
+        for c in cand:
+            pred = [v > c for v in s]
+            p, r = precision_recall(pred, lab)
+            f = f_beta(p, r, 1.0)
+            if best is None or f > best[0]:
+                best = (f, float(c), p, r)
+        fs.append(best[0]); th.append(best[1]); ps.append(best[2]); rs.append(best[3])
+    return {"th": th, "f1": fs, "precision": ps, "recall": rs}
