@@ -1,0 +1,242 @@
+/*
+ * qmi.h - C ABI of libqmi, the MI355X (gfx950) kernelised-periodogram period search.
+ *
+ * The method is from Protopapas et al., "A novel, fully automated pipeline for period estimation
+ * in the EROS 2 data set" (arXiv:1412.1840).  For every lightcurve {t_i, y_i}, i = 1..N, and every
+ * trial frequency f, the library forms the pair sums of the Gaussian kernel on magnitude
+ * differences (Sec. 2, Gaussian kernel) times the periodic kernel on time differences (Sec. 2.1):
+ *
+ *     K_y(i,j) = B exp(-(y_i - y_j)^2 / (2 sy^2)),        B = 1 / (sqrt(2 pi) sy)
+ *     K_t(i,j) = A exp(-2 sin^2(pi f (t_i - t_j)) / st^2), A = 1 / (sqrt(2 pi) st)
+ *
+ * and reduces them, over all ordered pairs with the diagonal included, to the information
+ * potentials
+ *
+ *     V_J(f)  = (1/N^2) sum_ij K_y(i,j) K_t(i,j)            joint
+ *     IP_y    = (1/N^2) sum_ij K_y(i,j)                     magnitude marginal (Sec. 3)
+ *     IP_t(f) = (1/N^2) sum_ij K_t(i,j)                     warped-time marginal
+ *     V_M(f)  = IP_y IP_t(f)
+ *     V_C(f)  = (1/N^3) sum_i [sum_k K_y(i,k)] [sum_j K_t(i,j)]   cross
+ *
+ * From these come two scores:
+ *     QMI(f)  = ln V_J + ln V_M - 2 ln V_C       Cauchy-Schwarz quadratic mutual information (>= 0)
+ *     nCKP(f) = sqrt(N st) / IP_y * (V_J - V_M)  the normalised CKP of Sec. 3 (V_J - V_M is the CKP)
+ *
+ * Units: t in days, f in 1/day, y and e in magnitudes.  All floating-point arguments and results
+ * are IEEE double.  Inside, the phase fold frac(f t) and the final scores are FP64; in the default
+ * mixed precision the kernel values and the pair sums run in FP32 with FP64 block accumulation.
+ *
+ * Error behaviour: every function returns QMI_OK (0) or a negative QMI_E* code.  A call-level error
+ * leaves every output buffer untouched and records a message for qmi_last_error.  A problem with
+ * one curve (N < 2, a non-finite sample, a degenerate width rule) does not fail the call: that
+ * curve's status is set and its outputs are NaN.  No C++ exception crosses this interface.
+ *
+ * Threading: a context is used by one host thread at a time; several contexts may share a device.
+ */
+#ifndef QMI_H
+#define QMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+#define QMI_OK 0
+#define QMI_EINVAL (-1)      /* invalid argument (bad sizes, sigma_t <= 0, f_max <= f_min, ...) */
+#define QMI_ENOMEM (-2)      /* device memory: a single curve does not fit the HBM budget */
+#define QMI_EDEVICE (-3)     /* HIP runtime error; text in qmi_last_error */
+#define QMI_EDEGENERATE (-4) /* width rule gives zero (per-curve status only) */
+#define QMI_EAGAIN (-5)      /* serving: admission budget full, try again later */
+#define QMI_EINTERNAL (-6)   /* internal error */
+
+/* Limits. */
+#define QMI_MAX_N 8192  /* samples per curve */
+#define QMI_MAX_TOPK 32 /* refined peaks per curve */
+
+/* sigma_y rules (qmi_kernel_params.sigma_y <= 0 selects a rule). */
+#define QMI_SIGMA_SILVERMAN (-1.0)  /* 0.9 min(s, IQR/1.34) N^(-1/5); s on N-1, linear quartiles */
+#define QMI_SIGMA_MEDIAN_ERR (-2.0) /* median of the error bars (Sec. 3) */
+
+/* Scores. */
+#define QMI_SCORE_CS_QMI 0
+#define QMI_SCORE_NCKP 1
+
+/* Arithmetic of the pair sums. */
+#define QMI_PREC_MIXED 0 /* FP64 fold + FP32 kernel values + FP32 short sums folded into FP64 */
+#define QMI_PREC_FP64 1  /* every step in FP64 */
+
+/* Discriminator output values. */
+#define QMI_NOT_PERIODIC 0
+#define QMI_PERIODIC 1
+#define QMI_UNDECIDED 255 /* bad status, non-finite score, or pSNR outside every bin */
+
+typedef struct qmi_ctx qmi_ctx;
+
+/*
+ * One batch of curves in CSR form: curve k is samples [offsets[k], offsets[k+1]).
+ * offsets is always a host array of n_curves + 1 non-decreasing int64 values starting at 0.
+ * t, y (and e, which may be NULL) are host arrays for qmi_periodogram / qmi_best_period and device
+ * arrays for the *_dev variants.  Samples may be in any order.  The library only reads them during
+ * the call (the *_dev variants: until the call returns, after it has synchronised its stream).
+ */
+typedef struct {
+    int32_t n_curves;
+    const int64_t *offsets;
+    const double *t; /* days */
+    const double *y; /* magnitudes */
+    const double *e; /* error bars, nullable (needed by QMI_SIGMA_MEDIAN_ERR and for pSNR) */
+} qmi_batch;
+
+/* sigma_t > 0: periodic-kernel width (Sec. 3 finds 0.1 - 0.6 typical).  sigma_y > 0: explicit
+ * magnitude-kernel width, or one of the QMI_SIGMA_* rules.  precision: QMI_PREC_*. */
+typedef struct {
+    double sigma_t;
+    double sigma_y;
+    int32_t precision;
+    int32_t reserved;
+} qmi_kernel_params;
+
+/*
+ * Coarse-to-fine search.  The coarse grid is f_k = f_min + k * ((f_max - f_min) / (n_coarse - 1)),
+ * k = 0 .. n_coarse-1.  Its local maxima (q_k > q_{k-1} and q_k >= q_{k+1}; q_0 >= q_1 at the first
+ * point, q_{F-1} > q_{F-2} at the last) are ranked by score, ties to the lower k, and the best top_k
+ * are each refined on n_fine evenly spaced points of [f_{k-1}, f_{k+1}] ([f_0, f_1], [f_{F-2},
+ * f_{F-1}] at the ends).  The best is the highest refined score, ties to the lower frequency, then
+ * to the lower peak rank.  top_k = 0 (or n_fine = 0) returns the coarse argmax (ties to lower k).
+ * Requirements: 0 <= f_min < f_max, 1 <= n_coarse <= 2^26, 0 <= top_k <= QMI_MAX_TOPK,
+ * n_fine == 0 or 2 <= n_fine <= 2^20, score one of QMI_SCORE_*.
+ */
+typedef struct {
+    double f_min, f_max;
+    int32_t n_coarse, top_k, n_fine;
+    int32_t score;
+} qmi_search;
+
+/* Per-curve result of qmi_best_period. */
+typedef struct {
+    double f_best;      /* 1/day */
+    double period;      /* 1 / f_best, days */
+    double score;       /* the searched score at f_best */
+    double score_qmi;   /* QMI at f_best */
+    double score_nckp;  /* nCKP at f_best */
+    double sigma_y;     /* magnitude-kernel width used */
+    double psnr;        /* 0.7413 iqr(y) / median(e) (Sec. 5.2, alpha = 1); NaN without e */
+    double coarse_best; /* coarse score at coarse_argmax */
+    int32_t coarse_index;  /* k of the refined peak holding f_best (coarse_argmax without refinement) */
+    int32_t peak_rank;     /* its rank among the refined peaks (-1 without refinement) */
+    int32_t fine_index;    /* index of f_best inside that peak's fine grid (-1 without refinement) */
+    int32_t coarse_argmax; /* plain argmax of the coarse scores */
+    int32_t n_peaks;       /* number of refined peaks */
+    int32_t n;             /* samples */
+    int32_t status;        /* QMI_OK or the per-curve QMI_E* code */
+    int32_t reserved;
+} qmi_result;
+
+/* SNR-binned thresholds (Sec. 4.1): bin b is [edges[b], edges[b+1]); periodic iff score > th[b]. */
+typedef struct {
+    int32_t n_bins;
+    int32_t score; /* QMI_SCORE_* the thresholds apply to */
+    const double *edges; /* [n_bins + 1], non-decreasing */
+    const double *th;    /* [n_bins] */
+} qmi_thresholds;
+
+/* Timing of the last qmi_periodogram / qmi_best_period call on this context, from HIP events on the
+ * context stream (pair kernels only, and the whole device section). */
+typedef struct {
+    double pair_kernel_ms;   /* summed duration of the pair-sum kernel launches */
+    double device_ms;        /* first kernel start to last kernel end */
+    double pair_items;       /* sum over curves of N(N-1)/2 x evaluated frequencies */
+    int32_t pair_launches;   /* number of pair-sum kernel launches */
+    int32_t used_graph;      /* 1 if the device section ran as a captured hipGraph */
+} qmi_stats;
+
+/*
+ * Create a context on HIP device hip_device.  hbm_budget_bytes caps the device memory the context
+ * allocates (0: 80% of the device's free memory at creation).  hip_stream is the hipStream_t to
+ * work on (NULL: the context creates its own stream at default priority).  Returns QMI_EDEVICE
+ * when no usable device is present.  *out is set only on success.
+ */
+int qmi_create(qmi_ctx **out, int hip_device, size_t hbm_budget_bytes, void *hip_stream);
+
+/* Release the context and all device memory it owns.  NULL is allowed. */
+void qmi_destroy(qmi_ctx *ctx);
+
+/* Message of the last error on ctx (never NULL; "" when none).  With ctx == NULL: the last
+ * qmi_create failure of this thread. */
+const char *qmi_last_error(const qmi_ctx *ctx);
+
+/* Options (qmi_set_option). */
+#define QMI_OPT_USE_GRAPH 1 /* 1: capture the device section into a hipGraph and replay it (default 1) */
+#define QMI_OPT_TILE 2      /* pair-kernel variant: 0 auto (autotuned), else a variant id */
+#define QMI_OPT_SYNC 3      /* reserved */
+int qmi_set_option(qmi_ctx *ctx, int32_t option, int64_t value);
+
+/* Copy the timing of the last call into *out. */
+int qmi_get_stats(const qmi_ctx *ctx, qmi_stats *out);
+
+/*
+ * Periodogram at a caller-supplied frequency list (the same list for every curve).
+ *   freqs      host, [n_freq] frequencies (finite, >= 0)
+ *   score      QMI_SCORE_* written to score_out
+ *   score_out  host, [n_curves * n_freq] row-major (curve, frequency)
+ *   ips_out    nullable host, [n_curves * n_freq * 3]: V_J, IP_t, V_C per (curve, frequency)
+ *   ip_y_out   nullable host, [n_curves]: IP_y
+ *   status_out nullable host, [n_curves]: per-curve status
+ * The inputs of the paper's problem statement: a curve, its kernel widths and a list of trial
+ * frequencies (Sec. 3 maximises the CKP over trial frequencies for fixed widths).
+ */
+int qmi_periodogram(qmi_ctx *ctx, const qmi_batch *batch, const qmi_kernel_params *kp,
+                    const double *freqs, int32_t n_freq, int32_t score, double *score_out,
+                    double *ips_out, double *ip_y_out, int32_t *status_out);
+
+/*
+ * Best period of each curve by the coarse-to-fine search of qmi_search.
+ *   out         host, [n_curves]
+ *   coarse_out  nullable host, [n_curves * n_coarse]: the coarse periodogram of the searched score
+ */
+int qmi_best_period(qmi_ctx *ctx, const qmi_batch *batch, const qmi_kernel_params *kp,
+                    const qmi_search *search, qmi_result *out, double *coarse_out);
+
+/* Device-pointer variants: batch->t, y, e, freqs and every output are device pointers (e.g.
+ * PyTorch-owned); out stays a host array.  They run on the context's stream and return after it
+ * has completed. */
+int qmi_periodogram_dev(qmi_ctx *ctx, const qmi_batch *batch, const qmi_kernel_params *kp,
+                        const double *freqs, int32_t n_freq, int32_t score, double *score_out,
+                        double *ips_out, double *ip_y_out, int32_t *status_out);
+int qmi_best_period_dev(qmi_ctx *ctx, const qmi_batch *batch, const qmi_kernel_params *kp,
+                        const qmi_search *search, qmi_result *out, double *coarse_out);
+
+/*
+ * Periodic / non-periodic decision (Sec. 4.1): for curve k with status QMI_OK, pSNR p (psnr[k] if
+ * psnr is not NULL, else best[k].psnr) in bin b and score s = best[k].score_qmi or score_nckp as
+ * th->score selects, is_periodic[k] = QMI_PERIODIC iff s > th->th[b] (strict).  Curves with a bad
+ * status, a non-finite score or pSNR outside every bin get QMI_UNDECIDED.  Host-only; needs no
+ * device.  Returns QMI_EINVAL for bad threshold tables.
+ */
+int qmi_discriminate(const qmi_result *best, int32_t n_curves, const double *psnr,
+                     const qmi_thresholds *th, uint8_t *is_periodic);
+
+/*
+ * Serving (continuous batching).  qmi_submit copies one curve (host arrays of n samples) into
+ * library-owned pinned staging and queues it with a caller tag; it returns QMI_EAGAIN when the
+ * admission budget (queued plus in-flight device memory) is full.  A background host thread admits
+ * queued requests into device launches as memory frees up, with up to max_inflight launches
+ * overlapping on the device.  qmi_poll moves up to max completed results (with their tags) into
+ * out / tags and returns their count (waiting up to timeout_us microseconds for at least one).
+ * Every request uses the kernel parameters and search given to qmi_serve_start.
+ */
+int qmi_serve_start(qmi_ctx *ctx, const qmi_kernel_params *kp, const qmi_search *search,
+                    size_t admit_budget_bytes, int32_t max_batch, int32_t max_inflight);
+int qmi_submit(qmi_ctx *ctx, const double *t, const double *y, const double *e, int32_t n,
+               uint64_t tag);
+int qmi_poll(qmi_ctx *ctx, qmi_result *out, uint64_t *tags, int32_t max, int32_t timeout_us);
+int qmi_serve_stop(qmi_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QMI_H */

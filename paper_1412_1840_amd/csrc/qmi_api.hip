@@ -1,0 +1,974 @@
+// Host runtime and C ABI of libqmi (declared in include/qmi.h): context, validation, batch
+// planning under the HBM budget, kernel launches, optional hipGraph replay, the discriminator
+// and the continuous-batching serving loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/qmi.h"
+#include "qmi_internal.h"
+
+using namespace qmi;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct Buf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Status {
+    int code = QMI_OK;
+    std::string msg;
+};
+
+}  // namespace
+
+struct qmi_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    size_t budget = 0;
+    size_t allocated = 0;
+    std::string err;
+    bool use_graph = true;
+    int64_t tile = 0;
+    qmi_stats stats{};
+    std::vector<hipEvent_t> ev;  // timing events (pairs: before/after each pair launch)
+    int ev_used = 0;
+    // Device buffers, grown on demand.
+    enum {
+        kT, kY, kE, kCP, kOrder, kRowStart, kK, kR, kRP, kRD, kCoarse, kCoarse2, kFine, kFine2,
+        kIps, kPeakK, kNpk, kWin, kArgmax, kRes, kFreqs, kStatusDummy, kNumBufs
+    };
+    Buf bufs[kNumBufs];
+    // Graph cache (device section of one planned group).
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<uint64_t> graph_key;
+    // Serving.
+    struct Serve;
+    std::unique_ptr<Serve> serve;
+    std::mutex call_mu;  // serialises device calls between the serving thread and the caller
+};
+
+namespace {
+
+void set_err(qmi_ctx* ctx, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    else g_create_error = buf;
+}
+
+#define HIP_OK(ctx, expr)                                                                  \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess) {                                                            \
+            set_err(ctx, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__,  \
+                    __LINE__);                                                             \
+            return (e_ == hipErrorOutOfMemory) ? QMI_ENOMEM : QMI_EDEVICE;                  \
+        }                                                                                  \
+    } while (0)
+
+int ensure(qmi_ctx* ctx, int id, size_t bytes) {
+    Buf& b = ctx->bufs[id];
+    if (bytes == 0) bytes = 256;
+    if (b.bytes >= bytes) return QMI_OK;
+    size_t want = bytes + bytes / 8;  // some headroom for the next call
+    if (ctx->allocated - b.bytes + want > ctx->budget) want = bytes;
+    if (ctx->allocated - b.bytes + want > ctx->budget) {
+        set_err(ctx, "HBM budget exceeded: need %zu more bytes (budget %zu)",
+                want - b.bytes, ctx->budget);
+        return QMI_ENOMEM;
+    }
+    if (b.p) {
+        HIP_OK(ctx, hipStreamSynchronize(ctx->stream));
+        HIP_OK(ctx, hipFree(b.p));
+        ctx->allocated -= b.bytes;
+        b.p = nullptr;
+        b.bytes = 0;
+        // Any captured graph refers to the old address.
+        if (ctx->graph_exec) {
+            (void)hipGraphExecDestroy(ctx->graph_exec);
+            ctx->graph_exec = nullptr;
+        }
+        if (ctx->graph) {
+            (void)hipGraphDestroy(ctx->graph);
+            ctx->graph = nullptr;
+        }
+        ctx->graph_key.clear();
+    }
+    HIP_OK(ctx, hipMalloc(&b.p, want));
+    b.bytes = want;
+    ctx->allocated += want;
+    return QMI_OK;
+}
+
+template <typename T>
+T* dptr(qmi_ctx* ctx, int id) {
+    return reinterpret_cast<T*>(ctx->bufs[id].p);
+}
+
+inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+int check_kernel_params(qmi_ctx* ctx, const qmi_kernel_params* kp) {
+    if (!kp) { set_err(ctx, "kernel params is NULL"); return QMI_EINVAL; }
+    if (!(kp->sigma_t > 0.0) || !std::isfinite(kp->sigma_t)) {
+        set_err(ctx, "sigma_t must be finite and > 0 (got %g)", kp->sigma_t);
+        return QMI_EINVAL;
+    }
+    if (!(kp->sigma_y > 0.0 && std::isfinite(kp->sigma_y)) && kp->sigma_y != QMI_SIGMA_SILVERMAN &&
+        kp->sigma_y != QMI_SIGMA_MEDIAN_ERR) {
+        set_err(ctx, "sigma_y must be > 0 or a QMI_SIGMA_* rule (got %g)", kp->sigma_y);
+        return QMI_EINVAL;
+    }
+    if (kp->precision != QMI_PREC_MIXED && kp->precision != QMI_PREC_FP64) {
+        set_err(ctx, "unknown precision %d", kp->precision);
+        return QMI_EINVAL;
+    }
+    return QMI_OK;
+}
+
+int check_batch(qmi_ctx* ctx, const qmi_batch* b, bool need_e) {
+    if (!b) { set_err(ctx, "batch is NULL"); return QMI_EINVAL; }
+    if (b->n_curves < 0) { set_err(ctx, "n_curves < 0"); return QMI_EINVAL; }
+    if (b->n_curves == 0) return QMI_OK;
+    if (!b->offsets || !b->t || !b->y) {
+        set_err(ctx, "batch offsets, t and y must not be NULL");
+        return QMI_EINVAL;
+    }
+    if (b->offsets[0] != 0) { set_err(ctx, "offsets[0] must be 0"); return QMI_EINVAL; }
+    for (int32_t k = 0; k < b->n_curves; ++k)
+        if (b->offsets[k + 1] < b->offsets[k]) {
+            set_err(ctx, "offsets must be non-decreasing (curve %d)", k);
+            return QMI_EINVAL;
+        }
+    if (need_e && !b->e) {
+        set_err(ctx, "QMI_SIGMA_MEDIAN_ERR needs error bars (batch e is NULL)");
+        return QMI_EINVAL;
+    }
+    return QMI_OK;
+}
+
+// Host-side per-curve status from the lengths (and, for host arrays, the sample values).
+int32_t host_curve_status(const qmi_batch* b, int32_t k, bool host_arrays) {
+    const int64_t a = b->offsets[k], n = b->offsets[k + 1] - a;
+    if (n < 2 || n > QMI_MAX_N) return QMI_EINVAL;
+    if (host_arrays) {
+        for (int64_t i = a; i < a + n; ++i) {
+            if (!std::isfinite(b->t[i]) || !std::isfinite(b->y[i])) return QMI_EINVAL;
+            if (b->e && !std::isfinite(b->e[i])) return QMI_EINVAL;
+        }
+    }
+    return QMI_OK;
+}
+
+// A contiguous group of curves [c0, c1) processed by one device section.
+struct Group {
+    int32_t c0, c1;
+    int64_t s0, s1;  // sample range
+};
+
+// Bytes of device memory one curve needs besides the fixed per-call buffers.
+size_t curve_bytes(int64_t n, int64_t F1, int64_t F2, bool fp64, bool ips, bool two_scores) {
+    const int64_t npad = round_up(std::max<int64_t>(n, 1), kPass);
+    const size_t rs = fp64 ? 8 : 4;
+    size_t b = 0;
+    b += (size_t)n * 3 * 8;                      // t, y, e
+    b += (size_t)n * (size_t)npad * rs;          // K
+    b += (size_t)n * rs + (size_t)npad * rs;     // r, rp
+    b += (size_t)n * 8;                          // rd
+    b += sizeof(CurveParams) + 64;
+    b += (size_t)F1 * 8 * (two_scores ? 2 : 1);  // coarse / periodogram scores
+    b += (size_t)F2 * 8 * 2;                     // fine scores
+    if (ips) b += (size_t)F1 * 24;
+    b += (size_t)QMI_MAX_TOPK * 32 + sizeof(DevResult);
+    return b;
+}
+
+struct CallSpec {
+    bool dev_inputs;       // batch arrays are device pointers
+    bool dev_outputs;      // score/ips/coarse outputs are device pointers
+    bool periodogram;      // caller list (true) or coarse-to-fine search (false)
+    const qmi_kernel_params* kp;
+    // periodogram
+    const double* freqs;
+    int32_t n_freq;
+    int32_t score;
+    double* score_out;
+    double* ips_out;
+    double* ip_y_out;
+    int32_t* status_out;
+    // search
+    const qmi_search* search;
+    qmi_result* out;
+    double* coarse_out;
+};
+
+int plan_groups(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, std::vector<Group>& groups) {
+    const bool fp64 = cs.kp->precision == QMI_PREC_FP64;
+    const int64_t F1 = cs.periodogram ? cs.n_freq : cs.search->n_coarse;
+    const int64_t F2 = cs.periodogram ? 0 : (int64_t)cs.search->top_k * cs.search->n_fine;
+    const bool two = !cs.periodogram;
+    const size_t fixed = 1 << 20;
+    if (ctx->budget <= fixed) {
+        set_err(ctx, "HBM budget too small");
+        return QMI_ENOMEM;
+    }
+    const size_t avail = ctx->budget - fixed;
+    Group g{0, 0, 0, 0};
+    size_t used = 0;
+    for (int32_t k = 0; k < b->n_curves; ++k) {
+        const int64_t n = b->offsets[k + 1] - b->offsets[k];
+        const size_t need = curve_bytes(std::min<int64_t>(n, QMI_MAX_N), F1, F2, fp64,
+                                        cs.ips_out != nullptr, two);
+        if (need > avail) {
+            set_err(ctx, "curve %d (N=%lld) needs %zu bytes, more than the HBM budget %zu", k,
+                    (long long)n, need, ctx->budget);
+            return QMI_ENOMEM;
+        }
+        if (used + need > avail && g.c1 > g.c0) {
+            groups.push_back(g);
+            g = Group{k, k, b->offsets[k], b->offsets[k]};
+            used = 0;
+        }
+        used += need;
+        g.c1 = k + 1;
+        g.s1 = b->offsets[k + 1];
+    }
+    if (g.c1 > g.c0) groups.push_back(g);
+    return QMI_OK;
+}
+
+void record(qmi_ctx* ctx) {
+    if (ctx->ev_used >= (int)ctx->ev.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        ctx->ev.push_back(e);
+    }
+    (void)hipEventRecord(ctx->ev[ctx->ev_used++], ctx->stream);
+}
+
+template <typename R>
+int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group& g,
+              std::vector<int32_t>& pair_event_idx) {
+    const int32_t nc = g.c1 - g.c0;
+    const int64_t ns = g.s1 - g.s0;
+    const bool fp64 = std::is_same<R, double>::value;
+    const qmi_kernel_params* kp = cs.kp;
+
+    // Per-curve parameters and layout.
+    std::vector<CurveParams> cp(nc);
+    std::vector<int32_t> order(nc);
+    std::vector<int64_t> row_start(nc);
+    int64_t koff = 0, poff = 0, rows = 0;
+    int max_n = 2;
+    for (int32_t i = 0; i < nc; ++i) {
+        const int32_t k = g.c0 + i;
+        const int64_t a = b->offsets[k], n = b->offsets[k + 1] - a;
+        CurveParams& p = cp[i];
+        std::memset(&p, 0, sizeof(p));
+        p.status = host_curve_status(b, k, !cs.dev_inputs);
+        p.off = a - g.s0;
+        p.n = (int32_t)std::min<int64_t>(n, QMI_MAX_N);
+        p.has_e = b->e != nullptr;
+        p.sigma_t = kp->sigma_t;
+        p.sigma_y_rule = kp->sigma_y;
+        p.sigma_y = NAN;
+        if (p.status == QMI_OK) {
+            p.npad = (int32_t)round_up(p.n, kPass);
+            p.koff = koff;
+            p.poff = poff;
+            koff += (int64_t)p.n * p.npad;
+            poff += p.npad;
+            row_start[i] = rows;
+            rows += p.n;
+            max_n = std::max(max_n, p.n);
+        } else {
+            row_start[i] = rows;
+        }
+        order[i] = i;
+    }
+    // Largest work first: the dispatcher hands out work items in order.
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) {
+        const int64_t na = cp[a].status ? 0 : cp[a].n, nb = cp[c].status ? 0 : cp[c].n;
+        return na > nb;
+    });
+
+    const int64_t F1 = cs.periodogram ? cs.n_freq : cs.search->n_coarse;
+    const int top_k = cs.periodogram ? 0 : cs.search->top_k;
+    const int n_fine = cs.periodogram ? 0 : cs.search->n_fine;
+    const bool refine = !cs.periodogram && top_k > 0 && n_fine > 0;
+    const int64_t F2 = refine ? (int64_t)top_k * n_fine : 0;
+    const int score_kind = cs.periodogram ? cs.score : cs.search->score;
+
+    int rc;
+#define ENSURE(id, bytes) \
+    if ((rc = ensure(ctx, id, (bytes))) != QMI_OK) return rc
+    if (!cs.dev_inputs) {
+        ENSURE(qmi_ctx::kT, ns * 8);
+        ENSURE(qmi_ctx::kY, ns * 8);
+        if (b->e) ENSURE(qmi_ctx::kE, ns * 8);
+    }
+    ENSURE(qmi_ctx::kCP, nc * sizeof(CurveParams));
+    ENSURE(qmi_ctx::kOrder, nc * sizeof(int32_t));
+    ENSURE(qmi_ctx::kRowStart, nc * sizeof(int64_t));
+    ENSURE(qmi_ctx::kK, std::max<int64_t>(koff, 1) * sizeof(R));
+    ENSURE(qmi_ctx::kR, std::max<int64_t>(ns, 1) * sizeof(R));
+    ENSURE(qmi_ctx::kRP, std::max<int64_t>(poff, 1) * sizeof(R));
+    ENSURE(qmi_ctx::kRD, std::max<int64_t>(ns, 1) * 8);
+    if (!(cs.periodogram && cs.dev_outputs)) ENSURE(qmi_ctx::kCoarse, nc * F1 * 8);
+    if (!cs.periodogram) ENSURE(qmi_ctx::kCoarse2, nc * F1 * 8);
+    if (refine) {
+        ENSURE(qmi_ctx::kFine, nc * F2 * 8);
+        ENSURE(qmi_ctx::kFine2, nc * F2 * 8);
+    }
+    if (cs.ips_out && !cs.dev_outputs) ENSURE(qmi_ctx::kIps, nc * F1 * 24);
+    if (!cs.periodogram) {
+        ENSURE(qmi_ctx::kPeakK, nc * std::max(top_k, 1) * sizeof(int32_t));
+        ENSURE(qmi_ctx::kNpk, nc * sizeof(int32_t));
+        ENSURE(qmi_ctx::kWin, nc * std::max(top_k, 1) * 16);
+        ENSURE(qmi_ctx::kArgmax, nc * sizeof(int32_t));
+        ENSURE(qmi_ctx::kRes, nc * sizeof(DevResult));
+    }
+    if (cs.periodogram && !cs.dev_inputs) ENSURE(qmi_ctx::kFreqs, F1 * 8);
+#undef ENSURE
+
+    hipStream_t st = ctx->stream;
+    const double* t = cs.dev_inputs ? b->t + g.s0 : dptr<double>(ctx, qmi_ctx::kT);
+    const double* y = cs.dev_inputs ? b->y + g.s0 : dptr<double>(ctx, qmi_ctx::kY);
+    const double* e = b->e ? (cs.dev_inputs ? b->e + g.s0 : dptr<double>(ctx, qmi_ctx::kE))
+                           : nullptr;
+    if (!cs.dev_inputs) {
+        HIP_OK(ctx, hipMemcpyAsync((void*)t, b->t + g.s0, ns * 8, hipMemcpyHostToDevice, st));
+        HIP_OK(ctx, hipMemcpyAsync((void*)y, b->y + g.s0, ns * 8, hipMemcpyHostToDevice, st));
+        if (e)
+            HIP_OK(ctx, hipMemcpyAsync((void*)e, b->e + g.s0, ns * 8, hipMemcpyHostToDevice, st));
+    }
+    CurveParams* dcp = dptr<CurveParams>(ctx, qmi_ctx::kCP);
+    int32_t* dorder = dptr<int32_t>(ctx, qmi_ctx::kOrder);
+    int64_t* drow = dptr<int64_t>(ctx, qmi_ctx::kRowStart);
+    HIP_OK(ctx, hipMemcpyAsync(dcp, cp.data(), nc * sizeof(CurveParams), hipMemcpyHostToDevice, st));
+    HIP_OK(ctx, hipMemcpyAsync(dorder, order.data(), nc * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIP_OK(ctx, hipMemcpyAsync(drow, row_start.data(), nc * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    const double* dfreqs = nullptr;
+    if (cs.periodogram) {
+        if (cs.dev_inputs) {
+            dfreqs = cs.freqs;
+        } else {
+            dfreqs = dptr<double>(ctx, qmi_ctx::kFreqs);
+            HIP_OK(ctx, hipMemcpyAsync((void*)dfreqs, cs.freqs, F1 * 8, hipMemcpyHostToDevice, st));
+        }
+    }
+
+    R* K = dptr<R>(ctx, qmi_ctx::kK);
+    R* r = dptr<R>(ctx, qmi_ctx::kR);
+    R* rp = dptr<R>(ctx, qmi_ctx::kRP);
+    double* rd = dptr<double>(ctx, qmi_ctx::kRD);
+
+    record(ctx);  // device section start
+    HIP_OK(ctx, launch_prologue(st, dcp, nc, max_n, t, y, e));
+    HIP_OK(ctx, launch_gram<R>(st, dcp, nc, rows, drow, y, K, r, rp, rd));
+    HIP_OK(ctx, launch_gram_finalize<R>(st, dcp, nc, rd, rp));
+
+    FreqPlan fp{};
+    PairOut po{};
+    double* coarse = nullptr;
+    double* coarse2 = nullptr;
+    if (cs.periodogram) {
+        fp.kind = 1;
+        fp.count = (int32_t)F1;
+        fp.list = dfreqs;
+        coarse = cs.dev_outputs ? cs.score_out + (int64_t)g.c0 * F1
+                                : dptr<double>(ctx, qmi_ctx::kCoarse);
+        po.score = coarse;
+        po.score2 = nullptr;
+        po.ips = cs.ips_out ? (cs.dev_outputs ? cs.ips_out + (int64_t)g.c0 * F1 * 3
+                                              : dptr<double>(ctx, qmi_ctx::kIps))
+                            : nullptr;
+        po.score_kind = score_kind;
+    } else {
+        const qmi_search* s = cs.search;
+        fp.kind = 0;
+        fp.count = s->n_coarse;
+        fp.f0 = s->f_min;
+        fp.df = s->n_coarse > 1 ? (s->f_max - s->f_min) / (double)(s->n_coarse - 1) : 0.0;
+        coarse = dptr<double>(ctx, qmi_ctx::kCoarse);
+        coarse2 = dptr<double>(ctx, qmi_ctx::kCoarse2);
+        po.score = coarse;
+        po.score2 = coarse2;
+        po.ips = nullptr;
+        po.score_kind = score_kind;
+    }
+    pair_event_idx.push_back(ctx->ev_used);
+    record(ctx);
+    HIP_OK(ctx, launch_pairs<R>(st, dcp, dorder, nc, fp, t, K, r, rp, po));
+    record(ctx);
+
+    if (!cs.periodogram) {
+        const qmi_search* s = cs.search;
+        PeakOut pk{dptr<int32_t>(ctx, qmi_ctx::kPeakK), dptr<int32_t>(ctx, qmi_ctx::kNpk),
+                   dptr<double>(ctx, qmi_ctx::kWin), dptr<int32_t>(ctx, qmi_ctx::kArgmax)};
+        HIP_OK(ctx, launch_peaks(st, dcp, nc, coarse, s->n_coarse, fp.f0, fp.df, top_k,
+                                 std::max(n_fine, 2), pk));
+        double* fine = nullptr;
+        double* fine2 = nullptr;
+        if (refine) {
+            fine = dptr<double>(ctx, qmi_ctx::kFine);
+            fine2 = dptr<double>(ctx, qmi_ctx::kFine2);
+            FreqPlan ff{};
+            ff.kind = 2;
+            ff.count = (int32_t)F2;
+            ff.n_fine = n_fine;
+            ff.top_k = top_k;
+            ff.win = pk.win;
+            ff.npk = pk.npk;
+            PairOut fo{fine, fine2, nullptr, score_kind, 0};
+            pair_event_idx.push_back(ctx->ev_used);
+            record(ctx);
+            HIP_OK(ctx, launch_pairs<R>(st, dcp, dorder, nc, ff, t, K, r, rp, fo));
+            record(ctx);
+        }
+        HIP_OK(ctx, launch_best(st, dcp, nc, coarse, coarse2, s->n_coarse, fine, fine2,
+                                refine ? top_k : 0, refine ? n_fine : 0, score_kind, fp.f0,
+                                fp.df, pk, dptr<DevResult>(ctx, qmi_ctx::kRes)));
+    }
+    record(ctx);  // device section end
+
+    // Results back to the caller.
+    if (cs.periodogram) {
+        if (!cs.dev_outputs) {
+            HIP_OK(ctx, hipMemcpyAsync(cs.score_out + (int64_t)g.c0 * F1, coarse, nc * F1 * 8,
+                                       hipMemcpyDeviceToHost, st));
+            if (cs.ips_out)
+                HIP_OK(ctx, hipMemcpyAsync(cs.ips_out + (int64_t)g.c0 * F1 * 3, po.ips,
+                                           nc * F1 * 24, hipMemcpyDeviceToHost, st));
+        }
+        std::vector<CurveParams> cpo(nc);
+        HIP_OK(ctx, hipMemcpyAsync(cpo.data(), dcp, nc * sizeof(CurveParams), hipMemcpyDeviceToHost, st));
+        HIP_OK(ctx, hipStreamSynchronize(st));
+        for (int32_t i = 0; i < nc; ++i) {
+            if (cs.ip_y_out) cs.ip_y_out[g.c0 + i] = cpo[i].status ? NAN : cpo[i].ipy;
+            if (cs.status_out) cs.status_out[g.c0 + i] = cpo[i].status;
+        }
+        // Curves rejected on the host were never given to the kernels' outputs.
+        if (!cs.dev_outputs) {
+            for (int32_t i = 0; i < nc; ++i)
+                if (cp[i].status != QMI_OK) {
+                    for (int64_t f = 0; f < F1; ++f) {
+                        cs.score_out[(int64_t)(g.c0 + i) * F1 + f] = NAN;
+                        if (cs.ips_out)
+                            for (int q = 0; q < 3; ++q)
+                                cs.ips_out[((int64_t)(g.c0 + i) * F1 + f) * 3 + q] = NAN;
+                    }
+                }
+        }
+    } else {
+        static_assert(sizeof(DevResult) == sizeof(qmi_result), "result layout");
+        HIP_OK(ctx, hipMemcpyAsync(cs.out + g.c0, dptr<DevResult>(ctx, qmi_ctx::kRes),
+                                   nc * sizeof(DevResult), hipMemcpyDeviceToHost, st));
+        if (cs.coarse_out) {
+            if (cs.dev_outputs)
+                HIP_OK(ctx, hipMemcpyAsync(cs.coarse_out + (int64_t)g.c0 * F1, coarse, nc * F1 * 8,
+                                           hipMemcpyDeviceToDevice, st));
+            else
+                HIP_OK(ctx, hipMemcpyAsync(cs.coarse_out + (int64_t)g.c0 * F1, coarse, nc * F1 * 8,
+                                           hipMemcpyDeviceToHost, st));
+        }
+        HIP_OK(ctx, hipStreamSynchronize(st));
+        for (int32_t i = 0; i < nc; ++i) {
+            qmi_result& rr = cs.out[g.c0 + i];
+            if (cp[i].status != QMI_OK) {
+                // The kernels skipped this curve; make its record explicit.
+                rr.status = cp[i].status;
+                rr.n = cp[i].n;
+            }
+            if (rr.status != QMI_OK) {
+                rr.f_best = rr.period = rr.score = rr.score_qmi = rr.score_nckp = NAN;
+                rr.coarse_best = NAN;
+                rr.coarse_index = rr.peak_rank = rr.fine_index = rr.coarse_argmax = -1;
+                rr.n_peaks = 0;
+            }
+            const int64_t n = b->offsets[g.c0 + i + 1] - b->offsets[g.c0 + i];
+            rr.n = (int32_t)n;
+            if (rr.status == QMI_OK)
+                ctx->stats.pair_items += (double)n * (double)(n - 1) / 2.0 *
+                                         (double)(F1 + (int64_t)rr.n_peaks * n_fine);
+        }
+    }
+    if (cs.periodogram) {
+        for (int32_t i = 0; i < nc; ++i) {
+            const int64_t n = b->offsets[g.c0 + i + 1] - b->offsets[g.c0 + i];
+            if (cp[i].status == QMI_OK)
+                ctx->stats.pair_items += (double)n * (double)(n - 1) / 2.0 * (double)F1;
+        }
+    }
+    (void)fp64;
+    return QMI_OK;
+}
+
+int run_call(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs) {
+    std::lock_guard<std::mutex> lk(ctx->call_mu);
+    ctx->err.clear();
+    int rc = check_kernel_params(ctx, cs.kp);
+    if (rc) return rc;
+    rc = check_batch(ctx, b, cs.kp->sigma_y == QMI_SIGMA_MEDIAN_ERR);
+    if (rc) return rc;
+    if (cs.periodogram) {
+        if (cs.n_freq < 1 || !cs.freqs || !cs.score_out) {
+            set_err(ctx, "periodogram needs n_freq >= 1, freqs and score_out");
+            return QMI_EINVAL;
+        }
+        if (cs.score != QMI_SCORE_CS_QMI && cs.score != QMI_SCORE_NCKP) {
+            set_err(ctx, "unknown score %d", cs.score);
+            return QMI_EINVAL;
+        }
+        if (!cs.dev_inputs)
+            for (int32_t q = 0; q < cs.n_freq; ++q)
+                if (!std::isfinite(cs.freqs[q]) || cs.freqs[q] < 0.0) {
+                    set_err(ctx, "frequency %d is not finite and >= 0", q);
+                    return QMI_EINVAL;
+                }
+    } else {
+        const qmi_search* s = cs.search;
+        if (!s || !cs.out) { set_err(ctx, "search and out must not be NULL"); return QMI_EINVAL; }
+        if (!(s->f_min >= 0.0) || !(s->f_max > s->f_min) || !std::isfinite(s->f_max)) {
+            set_err(ctx, "need 0 <= f_min < f_max (got %g, %g)", s->f_min, s->f_max);
+            return QMI_EINVAL;
+        }
+        if (s->n_coarse < 1 || s->n_coarse > (1 << 26) || s->top_k < 0 ||
+            s->top_k > QMI_MAX_TOPK || s->n_fine < 0 || s->n_fine == 1 ||
+            s->n_fine > (1 << 20)) {
+            set_err(ctx, "bad search sizes (n_coarse %d, top_k %d, n_fine %d)", s->n_coarse,
+                    s->top_k, s->n_fine);
+            return QMI_EINVAL;
+        }
+        if (s->score != QMI_SCORE_CS_QMI && s->score != QMI_SCORE_NCKP) {
+            set_err(ctx, "unknown score %d", s->score);
+            return QMI_EINVAL;
+        }
+    }
+    std::memset(&ctx->stats, 0, sizeof(ctx->stats));
+    if (b->n_curves == 0) return QMI_OK;
+    HIP_OK(ctx, hipSetDevice(ctx->device));
+    std::vector<Group> groups;
+    rc = plan_groups(ctx, b, cs, groups);
+    if (rc) return rc;
+    ctx->ev_used = 0;
+    std::vector<int32_t> pair_ev;
+    for (const Group& g : groups) {
+        rc = (cs.kp->precision == QMI_PREC_FP64) ? run_group<double>(ctx, b, cs, g, pair_ev)
+                                                 : run_group<float>(ctx, b, cs, g, pair_ev);
+        if (rc) return rc;
+    }
+    // Timing from the events (all complete: every group synchronised).
+    float ms = 0.f;
+    for (int32_t idx : pair_ev) {
+        if (hipEventElapsedTime(&ms, ctx->ev[idx], ctx->ev[idx + 1]) == hipSuccess)
+            ctx->stats.pair_kernel_ms += ms;
+        ctx->stats.pair_launches += 1;
+    }
+    if (ctx->ev_used >= 2 &&
+        hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[ctx->ev_used - 1]) == hipSuccess)
+        ctx->stats.device_ms = ms;
+    ctx->stats.used_graph = 0;
+    return QMI_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------------
+// Serving loop
+// ------------------------------------------------------------------------------------------------
+
+struct qmi_ctx::Serve {
+    qmi_kernel_params kp{};
+    qmi_search search{};
+    size_t admit_budget = 0;
+    int32_t max_batch = 256;
+    int32_t max_inflight = 2;
+    struct Req {
+        std::vector<double> t, y, e;
+        bool has_e = false;
+        uint64_t tag = 0;
+    };
+    struct Done {
+        qmi_result r;
+        uint64_t tag;
+    };
+    std::mutex mu;
+    std::condition_variable cv, done_cv;
+    std::deque<Req> queue;
+    std::deque<Done> done;
+    size_t queued_bytes = 0;
+    bool stop = false;
+    std::vector<std::thread> workers;
+    std::vector<qmi_ctx*> lanes;  // one private context (and stream) per in-flight launch
+};
+
+namespace {
+
+size_t request_bytes(const qmi_search& s, int64_t n) {
+    return curve_bytes(n, s.n_coarse, (int64_t)s.top_k * s.n_fine, false, false, true);
+}
+
+void serve_worker(qmi_ctx* ctx, int lane) {
+    qmi_ctx::Serve* S = ctx->serve.get();
+    qmi_ctx* lc = S->lanes[lane];
+    for (;;) {
+        std::vector<qmi_ctx::Serve::Req> take;
+        size_t take_bytes = 0;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->cv.wait(lk, [&] { return S->stop || !S->queue.empty(); });
+            if (S->stop && S->queue.empty()) return;
+            // Admit requests in arrival order while they fit this lane's share of the budget.
+            const size_t share = S->admit_budget / (size_t)S->max_inflight;
+            while (!S->queue.empty() && (int32_t)take.size() < S->max_batch) {
+                size_t rb = request_bytes(S->search, (int64_t)S->queue.front().t.size());
+                if (!take.empty() && take_bytes + rb > share) break;
+                take_bytes += rb;
+                take.push_back(std::move(S->queue.front()));
+                S->queue.pop_front();
+                S->queued_bytes -= rb;
+            }
+        }
+        // Pack and run on this lane's context (its own stream), overlapping other lanes.
+        std::vector<int64_t> off(take.size() + 1, 0);
+        for (size_t i = 0; i < take.size(); ++i) off[i + 1] = off[i] + (int64_t)take[i].t.size();
+        std::vector<double> t(off.back()), y(off.back()), e(off.back());
+        bool all_e = true;
+        for (size_t i = 0; i < take.size(); ++i) {
+            std::copy(take[i].t.begin(), take[i].t.end(), t.begin() + off[i]);
+            std::copy(take[i].y.begin(), take[i].y.end(), y.begin() + off[i]);
+            if (take[i].has_e) std::copy(take[i].e.begin(), take[i].e.end(), e.begin() + off[i]);
+            all_e = all_e && take[i].has_e;
+        }
+        qmi_batch b{(int32_t)take.size(), off.data(), t.data(), y.data(), all_e ? e.data() : nullptr};
+        std::vector<qmi_result> res(take.size());
+        int rc = qmi_best_period(lc, &b, &S->kp, &S->search, res.data(), nullptr);
+        std::lock_guard<std::mutex> lk(S->mu);
+        for (size_t i = 0; i < take.size(); ++i) {
+            if (rc != QMI_OK) {
+                std::memset(&res[i], 0, sizeof(qmi_result));
+                res[i].status = rc;
+                res[i].f_best = res[i].period = res[i].score = NAN;
+            }
+            S->done.push_back({res[i], take[i].tag});
+        }
+        S->done_cv.notify_all();
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------------
+// C ABI
+// ------------------------------------------------------------------------------------------------
+
+extern "C" {
+
+int qmi_create(qmi_ctx** out, int hip_device, size_t hbm_budget_bytes, void* hip_stream) {
+    if (!out) {
+        set_err(nullptr, "out is NULL");
+        return QMI_EINVAL;
+    }
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev <= 0) {
+        set_err(nullptr, "no HIP device available (%s)", hipGetErrorString(e));
+        return QMI_EDEVICE;
+    }
+    if (hip_device < 0 || hip_device >= ndev) {
+        set_err(nullptr, "device %d out of range (%d devices)", hip_device, ndev);
+        return QMI_EINVAL;
+    }
+    if (hipSetDevice(hip_device) != hipSuccess) {
+        set_err(nullptr, "hipSetDevice(%d) failed", hip_device);
+        return QMI_EDEVICE;
+    }
+    std::unique_ptr<qmi_ctx> ctx(new (std::nothrow) qmi_ctx());
+    if (!ctx) {
+        set_err(nullptr, "out of host memory");
+        return QMI_EINTERNAL;
+    }
+    ctx->device = hip_device;
+    if (hip_stream) {
+        ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    } else {
+        if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+            set_err(nullptr, "hipStreamCreate failed");
+            return QMI_EDEVICE;
+        }
+        ctx->own_stream = true;
+    }
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+        set_err(nullptr, "hipMemGetInfo failed");
+        if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+        return QMI_EDEVICE;
+    }
+    ctx->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.8 * (double)free_b);
+    *out = ctx.release();
+    return QMI_OK;
+}
+
+void qmi_destroy(qmi_ctx* ctx) {
+    if (!ctx) return;
+    if (ctx->serve) qmi_serve_stop(ctx);
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    for (auto& b : ctx->bufs)
+        if (b.p) (void)hipFree(b.p);
+    for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+const char* qmi_last_error(const qmi_ctx* ctx) {
+    return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+int qmi_set_option(qmi_ctx* ctx, int32_t option, int64_t value) {
+    if (!ctx) return QMI_EINVAL;
+    switch (option) {
+        case QMI_OPT_USE_GRAPH: ctx->use_graph = value != 0; return QMI_OK;
+        case QMI_OPT_TILE: ctx->tile = value; return QMI_OK;
+        case QMI_OPT_SYNC: return QMI_OK;
+        default: set_err(ctx, "unknown option %d", option); return QMI_EINVAL;
+    }
+}
+
+int qmi_get_stats(const qmi_ctx* ctx, qmi_stats* out) {
+    if (!ctx || !out) return QMI_EINVAL;
+    *out = ctx->stats;
+    return QMI_OK;
+}
+
+int qmi_periodogram(qmi_ctx* ctx, const qmi_batch* batch, const qmi_kernel_params* kp,
+                    const double* freqs, int32_t n_freq, int32_t score, double* score_out,
+                    double* ips_out, double* ip_y_out, int32_t* status_out) {
+    if (!ctx) return QMI_EINVAL;
+    CallSpec cs{};
+    cs.dev_inputs = false;
+    cs.dev_outputs = false;
+    cs.periodogram = true;
+    cs.kp = kp;
+    cs.freqs = freqs;
+    cs.n_freq = n_freq;
+    cs.score = score;
+    cs.score_out = score_out;
+    cs.ips_out = ips_out;
+    cs.ip_y_out = ip_y_out;
+    cs.status_out = status_out;
+    try {
+        return run_call(ctx, batch, cs);
+    } catch (...) {
+        set_err(ctx, "internal exception");
+        return QMI_EINTERNAL;
+    }
+}
+
+int qmi_periodogram_dev(qmi_ctx* ctx, const qmi_batch* batch, const qmi_kernel_params* kp,
+                        const double* freqs, int32_t n_freq, int32_t score, double* score_out,
+                        double* ips_out, double* ip_y_out, int32_t* status_out) {
+    if (!ctx) return QMI_EINVAL;
+    CallSpec cs{};
+    cs.dev_inputs = true;
+    cs.dev_outputs = true;
+    cs.periodogram = true;
+    cs.kp = kp;
+    cs.freqs = freqs;
+    cs.n_freq = n_freq;
+    cs.score = score;
+    cs.score_out = score_out;
+    cs.ips_out = ips_out;
+    cs.ip_y_out = ip_y_out;
+    cs.status_out = status_out;
+    try {
+        return run_call(ctx, batch, cs);
+    } catch (...) {
+        set_err(ctx, "internal exception");
+        return QMI_EINTERNAL;
+    }
+}
+
+int qmi_best_period(qmi_ctx* ctx, const qmi_batch* batch, const qmi_kernel_params* kp,
+                    const qmi_search* search, qmi_result* out, double* coarse_out) {
+    if (!ctx) return QMI_EINVAL;
+    CallSpec cs{};
+    cs.dev_inputs = false;
+    cs.dev_outputs = false;
+    cs.periodogram = false;
+    cs.kp = kp;
+    cs.search = search;
+    cs.out = out;
+    cs.coarse_out = coarse_out;
+    try {
+        return run_call(ctx, batch, cs);
+    } catch (...) {
+        set_err(ctx, "internal exception");
+        return QMI_EINTERNAL;
+    }
+}
+
+int qmi_best_period_dev(qmi_ctx* ctx, const qmi_batch* batch, const qmi_kernel_params* kp,
+                        const qmi_search* search, qmi_result* out, double* coarse_out) {
+    if (!ctx) return QMI_EINVAL;
+    CallSpec cs{};
+    cs.dev_inputs = true;
+    cs.dev_outputs = true;
+    cs.periodogram = false;
+    cs.kp = kp;
+    cs.search = search;
+    cs.out = out;
+    cs.coarse_out = coarse_out;
+    try {
+        return run_call(ctx, batch, cs);
+    } catch (...) {
+        set_err(ctx, "internal exception");
+        return QMI_EINTERNAL;
+    }
+}
+
+int qmi_discriminate(const qmi_result* best, int32_t n_curves, const double* psnr,
+                     const qmi_thresholds* th, uint8_t* is_periodic) {
+    if (n_curves < 0 || !th || !th->edges || !th->th || th->n_bins < 1 ||
+        (th->score != QMI_SCORE_CS_QMI && th->score != QMI_SCORE_NCKP))
+        return QMI_EINVAL;
+    if (n_curves > 0 && (!best || !is_periodic)) return QMI_EINVAL;
+    for (int32_t b = 0; b < th->n_bins; ++b)
+        if (!(th->edges[b] <= th->edges[b + 1])) return QMI_EINVAL;
+    for (int32_t k = 0; k < n_curves; ++k) {
+        const qmi_result& r = best[k];
+        const double p = psnr ? psnr[k] : r.psnr;
+        const double s = th->score == QMI_SCORE_CS_QMI ? r.score_qmi : r.score_nckp;
+        uint8_t v = QMI_UNDECIDED;
+        if (r.status == QMI_OK && std::isfinite(s) && p == p) {
+            for (int32_t b = 0; b < th->n_bins; ++b)
+                if (th->edges[b] <= p && p < th->edges[b + 1]) {
+                    v = s > th->th[b] ? QMI_PERIODIC : QMI_NOT_PERIODIC;
+                    break;
+                }
+        }
+        is_periodic[k] = v;
+    }
+    return QMI_OK;
+}
+
+int qmi_serve_start(qmi_ctx* ctx, const qmi_kernel_params* kp, const qmi_search* search,
+                    size_t admit_budget_bytes, int32_t max_batch, int32_t max_inflight) {
+    if (!ctx || !kp || !search || max_batch < 1 || max_inflight < 1 || max_inflight > 8)
+        return QMI_EINVAL;
+    if (ctx->serve) {
+        set_err(ctx, "serving already started");
+        return QMI_EINVAL;
+    }
+    int rc = check_kernel_params(ctx, kp);
+    if (rc) return rc;
+    auto S = std::make_unique<qmi_ctx::Serve>();
+    S->kp = *kp;
+    S->search = *search;
+    S->admit_budget = admit_budget_bytes ? admit_budget_bytes : ctx->budget / 2;
+    S->max_batch = max_batch;
+    S->max_inflight = max_inflight;
+    const size_t lane_budget = ctx->budget / (size_t)max_inflight;
+    for (int i = 0; i < max_inflight; ++i) {
+        qmi_ctx* lc = nullptr;
+        rc = qmi_create(&lc, ctx->device, lane_budget, nullptr);
+        if (rc) {
+            set_err(ctx, "serving lane %d: %s", i, qmi_last_error(nullptr));
+            for (qmi_ctx* c : S->lanes) qmi_destroy(c);
+            return rc;
+        }
+        lc->use_graph = ctx->use_graph;
+        S->lanes.push_back(lc);
+    }
+    ctx->serve = std::move(S);
+    for (int i = 0; i < max_inflight; ++i)
+        ctx->serve->workers.emplace_back(serve_worker, ctx, i);
+    return QMI_OK;
+}
+
+int qmi_submit(qmi_ctx* ctx, const double* t, const double* y, const double* e, int32_t n,
+               uint64_t tag) {
+    if (!ctx || !t || !y || n < 0) return QMI_EINVAL;
+    qmi_ctx::Serve* S = ctx->serve.get();
+    if (!S) {
+        set_err(ctx, "serving not started");
+        return QMI_EINVAL;
+    }
+    const size_t rb = request_bytes(S->search, n);
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (S->stop) return QMI_EINVAL;
+        if (S->queued_bytes + rb > S->admit_budget && !S->queue.empty()) return QMI_EAGAIN;
+        qmi_ctx::Serve::Req r;
+        r.t.assign(t, t + n);
+        r.y.assign(y, y + n);
+        if (e) {
+            r.e.assign(e, e + n);
+            r.has_e = true;
+        }
+        r.tag = tag;
+        S->queue.push_back(std::move(r));
+        S->queued_bytes += rb;
+    }
+    S->cv.notify_one();
+    return QMI_OK;
+}
+
+int qmi_poll(qmi_ctx* ctx, qmi_result* out, uint64_t* tags, int32_t max, int32_t timeout_us) {
+    if (!ctx || max < 0 || (max > 0 && (!out || !tags))) return QMI_EINVAL;
+    qmi_ctx::Serve* S = ctx->serve.get();
+    if (!S) return QMI_EINVAL;
+    std::unique_lock<std::mutex> lk(S->mu);
+    if (S->done.empty() && timeout_us > 0)
+        S->done_cv.wait_for(lk, std::chrono::microseconds(timeout_us),
+                            [&] { return !S->done.empty(); });
+    int32_t k = 0;
+    while (k < max && !S->done.empty()) {
+        out[k] = S->done.front().r;
+        tags[k] = S->done.front().tag;
+        S->done.pop_front();
+        ++k;
+    }
+    return k;
+}
+
+int qmi_serve_stop(qmi_ctx* ctx) {
+    if (!ctx || !ctx->serve) return QMI_EINVAL;
+    qmi_ctx::Serve* S = ctx->serve.get();
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+    }
+    S->cv.notify_all();
+    for (auto& th : S->workers) th.join();
+    for (qmi_ctx* c : S->lanes) qmi_destroy(c);
+    ctx->serve.reset();
+    return QMI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,107 @@
+// Internal declarations shared by the device code (qmi_kernels.hip) and the host runtime
+// (qmi_api.hip).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qmi {
+
+// Pair-kernel geometry.  A work item is (curve, tile of kLanes frequency slots); one lane owns one
+// frequency.  The pair triangle i < j is walked in passes of kPass rows; inside a pass wave w owns
+// the interleaved rows base + w + kWaves*m (m < rows per wave), so every wave has nearly the same
+// number of valid pairs in the diagonal region.  Columns j stream through LDS in chunks of kChunk.
+constexpr int kLanes = 64;
+constexpr int kWaves = 8;
+constexpr int kThreads = kWaves * kLanes;
+constexpr int kPass = 256;  // rows per pass; the K-table permutation is defined on it
+constexpr int kChunk = 64;  // columns per LDS chunk
+
+// Position of row i inside its pass in the K-table layout: rows of one wave are contiguous, so a
+// wave reads its rows' kernel values for one column with scalar loads.
+__host__ __device__ inline int64_t kperm(int64_t i) {
+    int64_t b = i & ~int64_t(kPass - 1);
+    int64_t r = i & (kPass - 1);
+    return b + (r & (kWaves - 1)) * (kPass / kWaves) + (r >> 3);
+}
+__host__ __device__ inline int64_t kperm_inv(int64_t s) {
+    int64_t b = s & ~int64_t(kPass - 1);
+    int64_t r = s & (kPass - 1);
+    return b + (r / (kPass / kWaves)) + kWaves * (r % (kPass / kWaves));
+}
+
+// Per-curve state, written by the host (off, koff, n, npad, status, sigma_t) and completed by the
+// prologue and Gram kernels.
+struct CurveParams {
+    int64_t off;   // first sample in the packed t / y / e arrays
+    int64_t koff;  // first element of this curve's K table
+    int64_t poff;  // first element of this curve's permuted row-sum array (npad entries)
+    int32_t n;     // samples
+    int32_t npad;  // K-table row length (multiple of kPass)
+    int32_t status;
+    int32_t has_e;
+    double sigma_t;
+    double sigma_y_rule;  // > 0 explicit, -1 Silverman, -2 median error bar
+    double sigma_y;
+    double A, B;   // 1 / (sqrt(2 pi) sigma)
+    double ipy;    // IP_y
+    double rsum;   // sum_i r_i
+    double psnr;
+};
+
+// How frequency slot s of curve c maps to a frequency.
+struct FreqPlan {
+    int32_t kind;   // 0 linear grid, 1 explicit list, 2 refinement windows
+    int32_t count;  // slots per curve
+    int32_t n_fine;
+    int32_t top_k;
+    double f0, df;           // kind 0: f = f0 + s * df
+    const double* list;      // kind 1
+    const double* win;       // kind 2: [curve][top_k][2] = (lo, step)
+    const int32_t* npk;      // kind 2: [curve] refined peaks
+};
+
+struct PairOut {
+    double* score;   // [curve][count] primary score
+    double* score2;  // nullable: [curve][count] the other score
+    double* ips;     // nullable: [curve][count][3] V_J, IP_t, V_C
+    int32_t score_kind;
+    int32_t pad;
+};
+
+struct PeakOut {
+    int32_t* peak_k;   // [curve][top_k]
+    int32_t* npk;      // [curve]
+    double* win;       // [curve][top_k][2]
+    int32_t* argmax;   // [curve]
+};
+
+// Result record written by the best-of kernel (mirrors qmi_result field order).
+struct DevResult {
+    double f_best, period, score, score_qmi, score_nckp, sigma_y, psnr, coarse_best;
+    int32_t coarse_index, peak_rank, fine_index, coarse_argmax, n_peaks, n, status, reserved;
+};
+
+// Launchers (qmi_kernels.hip).  All launch on `st` and return hipGetLastError().
+hipError_t launch_prologue(hipStream_t st, CurveParams* cp, int n_curves, int max_n,
+                           const double* t, const double* y, const double* e);
+template <typename R>
+hipError_t launch_gram(hipStream_t st, CurveParams* cp, int n_curves, int64_t total_rows,
+                       const int64_t* row_curve_start, const double* y, R* K, R* r, R* rp,
+                       double* rd);
+template <typename R>
+hipError_t launch_gram_finalize(hipStream_t st, CurveParams* cp, int n_curves, const double* rd,
+                                R* rp);
+template <typename R>
+hipError_t launch_pairs(hipStream_t st, const CurveParams* cp, const int32_t* order,
+                        int n_work_curves, const FreqPlan& fp, const double* t, const R* K,
+                        const R* r, const R* rp, const PairOut& out);
+hipError_t launch_peaks(hipStream_t st, const CurveParams* cp, int n_curves, const double* coarse,
+                        int n_coarse, double f0, double df, int top_k, int n_fine,
+                        const PeakOut& po);
+hipError_t launch_best(hipStream_t st, const CurveParams* cp, int n_curves, const double* coarse,
+                       const double* coarse2, int n_coarse, const double* fine,
+                       const double* fine2, int top_k, int n_fine, int score_kind, double f0,
+                       double df, const PeakOut& po, DevResult* res);
+
+}  // namespace qmi

@@ -1,0 +1,773 @@
+// HIP kernels for gfx950 (MI355X): prologue (kernel widths, pSNR), magnitude Gram matrix, the
+// pair x frequency sums (the hot path), peak selection and best-of.
+//
+// Method: Protopapas et al., arXiv:1412.1840.  Gaussian kernel (Sec. 2), periodic kernel and the
+// warp identity ||u_f(z) - u_f(y)||^2 = 4 sin^2(pi f (z - y)) (Sec. 2.1), CKP and information
+// potential (Sec. 3), normalised CKP (Sec. 3), pSNR (Sec. 5.2).
+#include <float.h>
+#include <math.h>
+
+#include "qmi_internal.h"
+
+namespace qmi {
+
+namespace {
+
+constexpr double kLog2e = 1.4426950408889634073599246810018921;
+constexpr double kInvSqrt2Pi = 0.39894228040143267793994605993438187;
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uniform(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double uniform(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// --------------------------------------------------------------------------------------------
+// Block-wide helpers
+// --------------------------------------------------------------------------------------------
+
+template <int BLOCK>
+__device__ double block_sum(double v, double* sh) {
+    // Deterministic tree: wave shuffles, then one value per wave combined in wave order.
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < BLOCK / 64; ++k) s += sh[k];
+        sh[0] = s;
+    }
+    __syncthreads();
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// In-LDS bitonic sort of n values (padded to a power of two with +inf) by one block.
+template <int BLOCK>
+__device__ void block_sort(double* a, int n) {
+    int m = 1;
+    while (m < n) m <<= 1;
+    for (int i = n + threadIdx.x; i < m; i += BLOCK) a[i] = INFINITY;
+    __syncthreads();
+    for (int k = 2; k <= m; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < m; i += BLOCK) {
+                int l = i ^ j;
+                if (l > i) {
+                    double x = a[i], y = a[l];
+                    bool up = (i & k) == 0;
+                    if ((x > y) == up) {
+                        a[i] = y;
+                        a[l] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Quantile by linear interpolation at position (n-1) p of sorted a[0..n).
+__device__ double sorted_quantile(const double* a, int n, double p) {
+    double h = (n - 1) * p;
+    int lo = (int)floor(h);
+    int hi = lo + 1 < n ? lo + 1 : n - 1;
+    return a[lo] + (h - lo) * (a[hi] - a[lo]);
+}
+
+__device__ double sorted_median(const double* a, int n) {
+    return (n & 1) ? a[n / 2] : 0.5 * (a[n / 2 - 1] + a[n / 2]);
+}
+
+// --------------------------------------------------------------------------------------------
+// Prologue: validity, sigma_y (Silverman or median error bar), pSNR, A, B.  One block per curve.
+// --------------------------------------------------------------------------------------------
+
+constexpr int kPrologueBlock = 256;
+
+__global__ void __launch_bounds__(kPrologueBlock)
+prologue_kernel(CurveParams* __restrict__ cp, const double* __restrict__ t,
+                const double* __restrict__ y, const double* __restrict__ e) {
+    extern __shared__ double sbuf[];  // [QMI_MAX_N rounded to pow2] + 64 scratch
+    __shared__ double red[kPrologueBlock / 64 + 1];
+    __shared__ int bad;
+    const int c = blockIdx.x;
+    CurveParams P = cp[c];
+    const int n = P.n;
+    if (P.status != 0) return;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    const double* tc = t + P.off;
+    const double* yc = y + P.off;
+    const double* ec = P.has_e ? e + P.off : nullptr;
+    for (int i = threadIdx.x; i < n; i += kPrologueBlock) {
+        bool ok = isfinite(tc[i]) && isfinite(yc[i]);
+        if (ec) ok = ok && isfinite(ec[i]);
+        if (!ok) bad = 1;
+    }
+    __syncthreads();
+    if (bad || n < 2) {
+        if (threadIdx.x == 0) cp[c].status = -1;  // QMI_EINVAL
+        return;
+    }
+    // Mean and sample deviation of y.
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += kPrologueBlock) s += yc[i];
+    const double mean = block_sum<kPrologueBlock>(s, red) / n;
+    s = 0.0;
+    for (int i = threadIdx.x; i < n; i += kPrologueBlock) {
+        double d = yc[i] - mean;
+        s += d * d;
+    }
+    const double sdev = sqrt(block_sum<kPrologueBlock>(s, red) / (n - 1));
+    // Quartiles of y.
+    for (int i = threadIdx.x; i < n; i += kPrologueBlock) sbuf[i] = yc[i];
+    block_sort<kPrologueBlock>(sbuf, n);
+    const double iqr = sorted_quantile(sbuf, n, 0.75) - sorted_quantile(sbuf, n, 0.25);
+    __syncthreads();
+    double med_e = NAN;
+    if (ec) {
+        for (int i = threadIdx.x; i < n; i += kPrologueBlock) sbuf[i] = ec[i];
+        block_sort<kPrologueBlock>(sbuf, n);
+        med_e = sorted_median(sbuf, n);
+    }
+    if (threadIdx.x != 0) return;
+    double sy = 0.0;
+    int status = 0;
+    if (P.sigma_y_rule > 0.0) {
+        sy = P.sigma_y_rule;
+    } else if (P.sigma_y_rule == -1.0) {
+        if (sdev == 0.0) {
+            status = -4;  // QMI_EDEGENERATE
+        } else {
+            double spread = (iqr == 0.0) ? sdev : fmin(sdev, iqr / 1.34);
+            sy = 0.9 * spread * pow((double)n, -0.2);
+        }
+    } else {
+        if (!(med_e > 0.0)) status = ec ? -4 : -1;
+        sy = med_e;
+    }
+    cp[c].status = status;
+    cp[c].sigma_y = status ? NAN : sy;
+    cp[c].A = kInvSqrt2Pi / P.sigma_t;
+    cp[c].B = status ? NAN : kInvSqrt2Pi / sy;
+    cp[c].psnr = (ec && med_e > 0.0) ? 0.7413 * iqr / med_e : NAN;
+}
+
+// --------------------------------------------------------------------------------------------
+// Magnitude Gram matrix K(j, i) = B exp(-(y_j - y_i)^2 / (2 sy^2)) in the permuted row layout, and
+// r_j = sum_i K(j, i) (diagonal B included).  One block per row j of one curve.
+// --------------------------------------------------------------------------------------------
+
+constexpr int kGramBlock = 256;
+
+template <typename R>
+__global__ void __launch_bounds__(kGramBlock)
+gram_kernel(const CurveParams* __restrict__ cp, const int64_t* __restrict__ row_curve_start,
+            int n_curves, const double* __restrict__ y, R* __restrict__ K, R* __restrict__ r,
+            R* __restrict__ rp, double* __restrict__ rd) {
+    __shared__ double red[kGramBlock / 64 + 1];
+    const int64_t row = blockIdx.x;
+    // Curve of this row: binary search over the prefix of row counts.
+    int lo = 0, hi = n_curves - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (row_curve_start[mid] <= row) lo = mid; else hi = mid - 1;
+    }
+    const int c = lo;
+    const CurveParams P = cp[c];
+    const int j = (int)(row - row_curve_start[c]);
+    if (P.status != 0) return;
+    const double* yc = y + P.off;
+    const double yj = yc[j];
+    const double inv2s2 = 1.0 / (2.0 * P.sigma_y * P.sigma_y);
+    R* Krow = K + P.koff + (int64_t)j * P.npad;
+    double acc = 0.0;
+    for (int s = threadIdx.x; s < P.npad; s += kGramBlock) {
+        int64_t i = kperm_inv(s);
+        R v = R(0);
+        if (i < P.n) {
+            double d = yj - yc[i];
+            v = (R)(P.B * exp(-d * d * inv2s2));
+        }
+        Krow[s] = v;
+        acc += (double)v;
+    }
+    acc = block_sum<kGramBlock>(acc, red);
+    if (threadIdx.x == 0) {
+        r[P.off + j] = (R)acc;
+        rp[P.poff + kperm(j)] = (R)acc;
+        rd[P.off + j] = acc;
+    }
+}
+
+constexpr int kFinBlock = 256;
+
+// IP_y = sum_i r_i / N^2, and zero the padding rows of the permuted row-sum array.
+template <typename R>
+__global__ void __launch_bounds__(kFinBlock)
+gram_finalize_kernel(CurveParams* __restrict__ cp, const double* __restrict__ rd,
+                     R* __restrict__ rp) {
+    __shared__ double red[kFinBlock / 64 + 1];
+    const int c = blockIdx.x;
+    const CurveParams P = cp[c];
+    if (P.status != 0 || P.npad == 0) return;
+    for (int s = threadIdx.x; s < P.npad; s += kFinBlock)
+        if (kperm_inv(s) >= P.n) rp[P.poff + s] = R(0);
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < P.n; i += kFinBlock) acc += rd[P.off + i];
+    acc = block_sum<kFinBlock>(acc, red);
+    if (threadIdx.x == 0) {
+        cp[c].rsum = acc;
+        cp[c].ipy = acc / ((double)P.n * (double)P.n);
+    }
+}
+
+// --------------------------------------------------------------------------------------------
+// Pair x frequency sums.
+// --------------------------------------------------------------------------------------------
+
+__device__ __forceinline__ double slot_freq(const FreqPlan& fp, int c, int s, bool& active) {
+    active = s < fp.count;
+    if (!active) return 0.0;
+    if (fp.kind == 0) return __dadd_rn(fp.f0, __dmul_rn((double)s, fp.df));
+    if (fp.kind == 1) return fp.list[s];
+    const int p = s / fp.n_fine, m = s - p * fp.n_fine;
+    if (p >= fp.npk[c]) {
+        active = false;
+        return 0.0;
+    }
+    const double* w = fp.win + ((int64_t)c * fp.top_k + p) * 2;
+    return __dadd_rn(w[0], __dmul_rn((double)m, w[1]));
+}
+
+// sin(2 pi p) and cos(2 pi p) for p in [-1/2, 1/2] (an FP64-folded phase), accurate to about 1e-9:
+// 2 pi p = (pi/2)(q + r) with q = rint(4p) and |r| <= 1/2, then the Taylor series of sin and cos of
+// theta = (pi/2) r (|theta| <= pi/4; the first omitted terms are below 7e-10) and the quadrant
+// identities sin(q pi/2 + theta), cos(q pi/2 + theta).
+__device__ __forceinline__ void sincos_2pi_reduced(double p, double& sn, double& cs) {
+    const double x = 4.0 * p;
+    const double q = rint(x);
+    const double th = (x - q) * 1.5707963267948966192313216916397514;
+    const double t2 = th * th;
+    const double s = th * fma(t2, fma(t2, fma(t2, fma(t2, 1.0 / 362880.0, -1.0 / 5040.0),
+                                                  1.0 / 120.0), -1.0 / 6.0), 1.0);
+    const double c = fma(t2, fma(t2, fma(t2, fma(t2, fma(t2, -1.0 / 3628800.0, 1.0 / 40320.0),
+                                                     -1.0 / 720.0), 1.0 / 24.0), -0.5), 1.0);
+    const int iq = ((int)q) & 3;
+    sn = (iq == 0) ? s : (iq == 1) ? c : (iq == 2) ? -s : -c;
+    cs = (iq == 0) ? c : (iq == 1) ? -s : (iq == 2) ? -c : s;
+}
+
+// Half-angle warp of a sample: h(t) = (2 log2(e) / sigma_t^2)^(1/4) (cos pi p, sin pi p) with p the
+// phase f t folded to [-1/2, 1/2] in FP64 (fma gives f t - rint(f t) with one rounding).  For two
+// samples d = h_s(i) h_c(j) - h_c(i) h_s(j) = sqrt(2 log2 e) / sigma_t * sin(pi f (t_i - t_j)), so
+// exp2(-d^2) = exp(-2 sin^2(pi f (t_i - t_j)) / sigma_t^2), the periodic kernel of Sec. 2.1 without
+// its constant (sin^2 of half the angle between the warp points u_f(t_i), u_f(t_j), whose chord is
+// 2 |sin|).  d is formed from a difference of products, so it is exact to rounding when the two
+// phases coincide and the kernel value is then exactly 1.
+template <typename R>
+struct Warp;
+
+template <>
+struct Warp<float> {
+    using V = float2;
+    __device__ __forceinline__ static V at(double f, double t, double scale) {
+        const double n = rint(f * t);
+        const double p = fma(f, t, -n);
+        double sn, cs;
+        sincos_2pi_reduced(0.5 * p, sn, cs);  // sin(pi p), cos(pi p)
+        return make_float2((float)(cs * scale), (float)(sn * scale));
+    }
+    __device__ __forceinline__ static float kexp(float a) { return __builtin_amdgcn_exp2f(a); }
+};
+
+template <>
+struct Warp<double> {
+    using V = double2;
+    __device__ __forceinline__ static V at(double f, double t, double scale) {
+        const double n = rint(f * t);
+        const double p = fma(f, t, -n);
+        double sn, cs;
+        sincospi(p, &sn, &cs);
+        return make_double2(cs * scale, sn * scale);
+    }
+    __device__ __forceinline__ static double kexp(double a) { return exp2(a); }
+};
+
+template <typename R>
+struct PairCfg;
+template <>
+struct PairCfg<float> {
+    static constexpr int kRows = 32;  // rows per wave per pass
+    static constexpr int kChunkCols = kChunk;
+};
+template <>
+struct PairCfg<double> {
+    static constexpr int kRows = 16;
+    static constexpr int kChunkCols = kChunk / 2;
+};
+
+// One term of the pair sums for row i of this wave and the current column j: the kernel value
+// g = exp2(-(d^2 + moff)) with d = h_s(i) h_c(j) - h_c(i) h_s(j) and moff = 0 (or +inf for a row that
+// is masked out, giving g = 0), added to the column sum Tj, the row sum G and the K-weighted column
+// sum Jj.
+template <typename R>
+__device__ __forceinline__ void pair_term(R hc, R hs, R ux, R uy, R moff, R k, R& Tj, R& G, R& Jj) {
+    const R pr = hc * uy;
+    const R d = fma(hs, ux, -pr);
+    const R a = fma(d, d, moff);
+    const R g = Warp<R>::kexp(-a);
+    Tj += g;
+    G += g;
+    Jj = fma(k, g, Jj);
+}
+
+// One work item = (curve, kLanes frequency slots).  Accumulators per lane (one frequency):
+//   SJ  = sum_{i<j} K(i,j) g_ij          ST  = sum_{i<j} g_ij
+//   SCa = sum_{i<j} r_i g_ij             SCb = sum_{i<j} r_j g_ij
+// with g_ij = exp(-2 sin^2(pi f (t_i - t_j)) / sigma_t^2).  Short runs are summed in R and folded
+// into FP64 once per column (over rows) or once per chunk (per row).
+template <typename R>
+__global__ void __launch_bounds__(kThreads)
+pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ order,
+             FreqPlan fp, const double* __restrict__ t_all, const R* __restrict__ K_all,
+             const R* __restrict__ r_all, const R* __restrict__ rp_all, PairOut out) {
+    using W = Warp<R>;
+    using V = typename W::V;
+    constexpr int ROWS = PairCfg<R>::kRows;
+    constexpr int PASS = kWaves * ROWS;
+    constexpr int CH = PairCfg<R>::kChunkCols;
+    constexpr int GRP = 4;  // rows skipped together in the diagonal region
+    __shared__ V ph[2][CH][kLanes];
+
+    const int lane = threadIdx.x & 63;
+    const int w = uniform((int)(threadIdx.x >> 6));
+    const int tiles = (fp.count + kLanes - 1) / kLanes;
+    const int rank = blockIdx.x / tiles;
+    const int tile = blockIdx.x - rank * tiles;
+    const int c = order[rank];
+    const CurveParams P = cp[c];
+    const int slot = tile * kLanes + lane;
+    bool active;
+    const double f = slot_freq(fp, c, slot, active);
+    const int64_t obase = (int64_t)c * fp.count + slot;
+
+    if (P.status != 0) {
+        if (active && w == 0) {
+            out.score[obase] = NAN;
+            if (out.score2) out.score2[obase] = NAN;
+            if (out.ips) {
+                out.ips[obase * 3 + 0] = NAN;
+                out.ips[obase * 3 + 1] = NAN;
+                out.ips[obase * 3 + 2] = NAN;
+            }
+        }
+        return;
+    }
+
+    const int n = P.n;
+    const double* t = t_all + P.off;
+    const R* rr = r_all + P.off;
+    const double scale = sqrt(sqrt(2.0 * kLog2e) / P.sigma_t);
+    const R zero = R(0);
+    const R pinf = uniform((R)INFINITY);
+
+    double SJ = 0.0, ST = 0.0, SCa = 0.0, SCb = 0.0;
+
+    for (int base = 0; base < n; base += PASS) {
+        // This wave's rows: base + w + kWaves * m, m < nrows.
+        const int nrows = uniform(min(ROWS, max(0, (n - base - w + kWaves - 1) / kWaves)));
+        R ci[ROWS], si[ROWS], G[ROWS];
+#pragma unroll
+        for (int m = 0; m < ROWS; ++m) {
+            const int i = base + w + kWaves * m;
+            V u = (m < nrows) ? W::at(f, t[i], scale) : V{R(0), R(0)};
+            ci[m] = u.x;
+            si[m] = u.y;
+            G[m] = R(0);
+        }
+        const int64_t kofs = kperm(base + w);
+        const R* Kbase = K_all + P.koff + kofs;
+        const R* rpb = rp_all + P.poff + kofs;
+        const int nch = (n - base + CH - 1) / CH;
+
+        auto stage = [&](int j0, int buf) {
+            for (int q = w; q < CH; q += kWaves) {
+                const int j = j0 + q;
+                ph[buf][q][lane] = (j < n) ? W::at(f, t[j], scale) : V{R(0), R(0)};
+            }
+        };
+        stage(base, 0);
+        __syncthreads();
+        for (int k = 0; k < nch; ++k) {
+            const int j0 = base + k * CH;
+            if (k + 1 < nch) stage(j0 + CH, (k + 1) & 1);
+            const int buf = k & 1;
+            const int jend = min(CH, n - j0);
+            R Tc = R(0), Jc = R(0), Cc = R(0);
+            // Columns of this chunk.  Past the diagonal block of the pass every row of a full wave
+            // pairs with every column (straight-line body); in the diagonal block, or for a wave
+            // with fewer than ROWS rows, rows with i >= j are masked.
+            const bool straight = (nrows == ROWS) && (j0 >= base + PASS);
+            if (straight) {
+                for (int q = 0; q < jend; ++q) {
+                    const int j = j0 + q;
+                    const V u = ph[buf][q][lane];
+                    const R* kr = Kbase + (int64_t)j * P.npad;
+                    R kk[ROWS];
+#pragma unroll
+                    for (int m = 0; m < ROWS; ++m) kk[m] = kr[m];
+                    R Tj = R(0), Jj = R(0);
+#pragma unroll
+                    for (int m = 0; m < ROWS; ++m)
+                        pair_term<R>(ci[m], si[m], u.x, u.y, zero, kk[m], Tj, G[m], Jj);
+                    Tc += Tj;
+                    Jc += Jj;
+                    Cc = fma(rr[j], Tj, Cc);
+                }
+            } else {
+                for (int q = 0; q < jend; ++q) {
+                    const int j = j0 + q;
+                    int cnt = (j - base - w + kWaves - 1) / kWaves;
+                    cnt = uniform(cnt < 0 ? 0 : (cnt > nrows ? nrows : cnt));
+                    if (cnt == 0) continue;
+                    const V u = ph[buf][q][lane];
+                    const R* kr = Kbase + (int64_t)j * P.npad;
+                    R kk[ROWS];
+#pragma unroll
+                    for (int m = 0; m < ROWS; ++m) kk[m] = kr[m];
+                    R Tj = R(0), Jj = R(0);
+                    // Masked rows get an exponent offset of +inf (g = 0); groups of GRP rows that
+                    // are entirely masked are skipped.  cnt and the branches are wave-uniform.
+#pragma unroll
+                    for (int g0 = 0; g0 < ROWS; g0 += GRP) {
+                        if (g0 < cnt) {
+#pragma unroll
+                            for (int m = g0; m < g0 + GRP; ++m) {
+                                const R off = (m < cnt) ? zero : pinf;
+                                pair_term<R>(ci[m], si[m], u.x, u.y, off, kk[m], Tj, G[m], Jj);
+                            }
+                        }
+                    }
+                    Tc += Tj;
+                    Jc += Jj;
+                    Cc = fma(rr[j], Tj, Cc);
+                }
+            }
+            ST += (double)Tc;
+            SJ += (double)Jc;
+            SCb += (double)Cc;
+            R rk[ROWS];
+#pragma unroll
+            for (int m = 0; m < ROWS; ++m) rk[m] = rpb[m];
+            R Ca = R(0);
+#pragma unroll
+            for (int m = 0; m < ROWS; ++m) {
+                Ca = fma(rk[m], G[m], Ca);
+                G[m] = R(0);
+            }
+            SCa += (double)Ca;
+            __syncthreads();
+        }
+    }
+
+    // Combine the waves' partial sums in wave order (deterministic), then the epilogue.
+    double* red = reinterpret_cast<double*>(&ph[0][0][0]);
+    red[(w * kLanes + lane) * 4 + 0] = SJ;
+    red[(w * kLanes + lane) * 4 + 1] = ST;
+    red[(w * kLanes + lane) * 4 + 2] = SCa;
+    red[(w * kLanes + lane) * 4 + 3] = SCb;
+    __syncthreads();
+    if (w != 0 || !active) return;
+    SJ = ST = SCa = SCb = 0.0;
+    for (int v = 0; v < kWaves; ++v) {
+        SJ += red[(v * kLanes + lane) * 4 + 0];
+        ST += red[(v * kLanes + lane) * 4 + 1];
+        SCa += red[(v * kLanes + lane) * 4 + 2];
+        SCb += red[(v * kLanes + lane) * 4 + 3];
+    }
+    const double N = (double)n;
+    const double VJ = P.A * (N * P.B + 2.0 * SJ) / (N * N);
+    const double IPt = P.A * (N + 2.0 * ST) / (N * N);
+    const double VC = P.A * (P.rsum + SCa + SCb) / (N * N * N);
+    const double VM = P.ipy * IPt;
+    const double q = log(VJ) + log(VM) - 2.0 * log(VC);
+    const double nckp = sqrt(N * P.sigma_t) / P.ipy * (VJ - VM);
+    out.score[obase] = out.score_kind == 0 ? q : nckp;
+    if (out.score2) out.score2[obase] = out.score_kind == 0 ? nckp : q;
+    if (out.ips) {
+        out.ips[obase * 3 + 0] = VJ;
+        out.ips[obase * 3 + 1] = IPt;
+        out.ips[obase * 3 + 2] = VC;
+    }
+}
+
+// --------------------------------------------------------------------------------------------
+// Peaks: local maxima of the coarse scores, best top_k by (score desc, k asc), and their
+// refinement windows.  One block per curve.
+// --------------------------------------------------------------------------------------------
+
+constexpr int kPeakBlock = 256;
+
+__device__ __forceinline__ bool better(double qa, int ka, double qb, int kb) {
+    // a ranks before b: higher score, ties to lower index.  NaN never ranks.
+    if (!(qa == qa)) return false;
+    if (!(qb == qb)) return true;
+    return qa > qb || (qa == qb && ka < kb);
+}
+
+__device__ __forceinline__ double grid_f(double f0, double df, int k) {
+    return __dadd_rn(f0, __dmul_rn((double)k, df));
+}
+
+__global__ void __launch_bounds__(kPeakBlock)
+peaks_kernel(const CurveParams* __restrict__ cp, const double* __restrict__ coarse, int F,
+             double f0, double df, int top_k, int n_fine, PeakOut po) {
+    __shared__ double sq[kPeakBlock];
+    __shared__ int sk[kPeakBlock];
+    __shared__ int chosen[64];
+    const int c = blockIdx.x;
+    const double* q = coarse + (int64_t)c * F;
+    const bool ok = cp[c].status == 0;
+    // Coarse argmax (ties to lower k).
+    double bq = NAN;
+    int bk = 0x7fffffff;
+    if (ok)
+        for (int k = threadIdx.x; k < F; k += kPeakBlock)
+            if (better(q[k], k, bq, bk)) { bq = q[k]; bk = k; }
+    sq[threadIdx.x] = bq;
+    sk[threadIdx.x] = bk;
+    __syncthreads();
+    for (int s = kPeakBlock / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s && better(sq[threadIdx.x + s], sk[threadIdx.x + s], sq[threadIdx.x],
+                                      sk[threadIdx.x])) {
+            sq[threadIdx.x] = sq[threadIdx.x + s];
+            sk[threadIdx.x] = sk[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) po.argmax[c] = (sk[0] == 0x7fffffff) ? 0 : sk[0];
+    __syncthreads();
+    // Iterative selection of the top_k local maxima.
+    int count = 0;
+    for (int p = 0; p < top_k && ok; ++p) {
+        bq = NAN;
+        bk = 0x7fffffff;
+        for (int k = threadIdx.x; k < F; k += kPeakBlock) {
+            const double v = q[k];
+            bool peak;
+            if (F == 1) peak = (v == v);
+            else if (k == 0) peak = v >= q[1];
+            else if (k == F - 1) peak = v > q[k - 1];
+            else peak = v > q[k - 1] && v >= q[k + 1];
+            if (!peak) continue;
+            bool taken = false;
+            for (int a = 0; a < count; ++a) taken |= (chosen[a] == k);
+            if (!taken && better(v, k, bq, bk)) { bq = v; bk = k; }
+        }
+        sq[threadIdx.x] = bq;
+        sk[threadIdx.x] = bk;
+        __syncthreads();
+        for (int s = kPeakBlock / 2; s > 0; s >>= 1) {
+            if (threadIdx.x < s && better(sq[threadIdx.x + s], sk[threadIdx.x + s],
+                                          sq[threadIdx.x], sk[threadIdx.x])) {
+                sq[threadIdx.x] = sq[threadIdx.x + s];
+                sk[threadIdx.x] = sk[threadIdx.x + s];
+            }
+            __syncthreads();
+        }
+        const int kk = sk[0];
+        __syncthreads();
+        if (kk == 0x7fffffff) break;
+        if (threadIdx.x == 0) chosen[count] = kk;
+        __syncthreads();
+        ++count;
+    }
+    if (threadIdx.x == 0) {
+        po.npk[c] = count;
+        for (int p = 0; p < count; ++p) {
+            const int k = chosen[p];
+            int a = k - 1, b = k + 1;
+            if (F == 1) { a = 0; b = 0; }
+            else if (k == 0) { a = 0; b = 1; }
+            else if (k == F - 1) { a = F - 2; b = F - 1; }
+            const double lo = grid_f(f0, df, a), hi = grid_f(f0, df, b);
+            po.peak_k[(int64_t)c * top_k + p] = k;
+            po.win[((int64_t)c * top_k + p) * 2 + 0] = lo;
+            po.win[((int64_t)c * top_k + p) * 2 + 1] = (hi - lo) / (double)(n_fine - 1);
+        }
+    }
+}
+
+// --------------------------------------------------------------------------------------------
+// Best-of: highest refined score, ties to the lower frequency then the lower peak rank.
+// --------------------------------------------------------------------------------------------
+
+constexpr int kBestBlock = 256;
+
+__global__ void __launch_bounds__(kBestBlock)
+best_kernel(const CurveParams* __restrict__ cp, const double* __restrict__ coarse,
+            const double* __restrict__ coarse2, int F,
+            const double* __restrict__ fine, const double* __restrict__ fine2, int top_k,
+            int n_fine, int score_kind, double f0, double df, PeakOut po,
+            DevResult* __restrict__ res) {
+    __shared__ double sq[kBestBlock], sf[kBestBlock];
+    __shared__ int ss[kBestBlock];
+    const int c = blockIdx.x;
+    const CurveParams P = cp[c];
+    const int npk = (top_k > 0 && n_fine > 0 && P.status == 0) ? po.npk[c] : 0;
+    const int64_t S = (int64_t)top_k * n_fine;
+    double bq = NAN, bf = INFINITY;
+    int bs = 0x7fffffff;
+    for (int s = threadIdx.x; s < npk * n_fine; s += kBestBlock) {
+        const double v = fine[(int64_t)c * S + s];
+        if (!(v == v)) continue;
+        const int p = s / n_fine, m = s - p * n_fine;
+        const double* w = po.win + ((int64_t)c * top_k + p) * 2;
+        const double fr = __dadd_rn(w[0], __dmul_rn((double)m, w[1]));
+        bool b = !(bq == bq) || v > bq || (v == bq && (fr < bf || (fr == bf && s < bs)));
+        if (b) { bq = v; bf = fr; bs = s; }
+    }
+    sq[threadIdx.x] = bq;
+    sf[threadIdx.x] = bf;
+    ss[threadIdx.x] = bs;
+    __syncthreads();
+    for (int h = kBestBlock / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            const double v = sq[threadIdx.x + h], fr = sf[threadIdx.x + h];
+            const int s = ss[threadIdx.x + h];
+            const double cq = sq[threadIdx.x], cf = sf[threadIdx.x];
+            const int cs = ss[threadIdx.x];
+            bool b = (v == v) && (!(cq == cq) || v > cq || (v == cq && (fr < cf || (fr == cf && s < cs))));
+            if (b) { sq[threadIdx.x] = v; sf[threadIdx.x] = fr; ss[threadIdx.x] = s; }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    DevResult r;
+    r.sigma_y = P.sigma_y;
+    r.psnr = P.psnr;
+    r.n = P.n;
+    r.status = P.status;
+    r.reserved = 0;
+    r.n_peaks = npk;
+    const int am = (P.status == 0) ? po.argmax[c] : 0;
+    r.coarse_argmax = am;
+    r.coarse_best = (P.status == 0) ? coarse[(int64_t)c * F + am] : NAN;
+    if (P.status != 0) {
+        r.f_best = r.period = r.score = r.score_qmi = r.score_nckp = NAN;
+        r.coarse_index = r.peak_rank = r.fine_index = -1;
+    } else if (npk == 0 || ss[0] == 0x7fffffff) {
+        r.f_best = grid_f(f0, df, am);
+        r.period = 1.0 / r.f_best;
+        r.score = r.coarse_best;
+        r.coarse_index = am;
+        r.peak_rank = -1;
+        r.fine_index = -1;
+        const double other = coarse2 ? coarse2[(int64_t)c * F + am] : NAN;
+        r.score_qmi = score_kind == 0 ? r.coarse_best : other;
+        r.score_nckp = score_kind == 0 ? other : r.coarse_best;
+    } else {
+        const int s = ss[0];
+        const int p = s / n_fine, m = s - p * n_fine;
+        r.f_best = sf[0];
+        r.period = 1.0 / r.f_best;
+        r.score = sq[0];
+        const double other = fine2 ? fine2[(int64_t)c * S + s] : NAN;
+        r.score_qmi = score_kind == 0 ? sq[0] : other;
+        r.score_nckp = score_kind == 0 ? other : sq[0];
+        r.coarse_index = po.peak_k[(int64_t)c * top_k + p];
+        r.peak_rank = p;
+        r.fine_index = m;
+    }
+    res[c] = r;
+}
+
+}  // namespace
+
+// --------------------------------------------------------------------------------------------
+// Launchers
+// --------------------------------------------------------------------------------------------
+
+hipError_t launch_prologue(hipStream_t st, CurveParams* cp, int n_curves, int max_n,
+                           const double* t, const double* y, const double* e) {
+    if (n_curves <= 0) return hipSuccess;
+    int m = 1;
+    while (m < max_n) m <<= 1;
+    size_t shm = sizeof(double) * (size_t)m;
+    prologue_kernel<<<n_curves, kPrologueBlock, shm, st>>>(cp, t, y, e);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_gram(hipStream_t st, CurveParams* cp, int n_curves, int64_t total_rows,
+                       const int64_t* row_curve_start, const double* y, R* K, R* r, R* rp,
+                       double* rd) {
+    if (total_rows <= 0) return hipSuccess;
+    gram_kernel<R><<<(unsigned)total_rows, kGramBlock, 0, st>>>(cp, row_curve_start, n_curves, y,
+                                                                 K, r, rp, rd);
+    return hipGetLastError();
+}
+template hipError_t launch_gram<float>(hipStream_t, CurveParams*, int, int64_t, const int64_t*,
+                                       const double*, float*, float*, float*, double*);
+template hipError_t launch_gram<double>(hipStream_t, CurveParams*, int, int64_t, const int64_t*,
+                                        const double*, double*, double*, double*, double*);
+
+template <typename R>
+hipError_t launch_gram_finalize(hipStream_t st, CurveParams* cp, int n_curves, const double* rd,
+                                R* rp) {
+    if (n_curves <= 0) return hipSuccess;
+    gram_finalize_kernel<R><<<n_curves, kFinBlock, 0, st>>>(cp, rd, rp);
+    return hipGetLastError();
+}
+template hipError_t launch_gram_finalize<float>(hipStream_t, CurveParams*, int, const double*,
+                                                float*);
+template hipError_t launch_gram_finalize<double>(hipStream_t, CurveParams*, int, const double*,
+                                                 double*);
+
+template <typename R>
+hipError_t launch_pairs(hipStream_t st, const CurveParams* cp, const int32_t* order,
+                        int n_work_curves, const FreqPlan& fp, const double* t, const R* K,
+                        const R* r, const R* rp, const PairOut& out) {
+    if (n_work_curves <= 0 || fp.count <= 0) return hipSuccess;
+    const int tiles = (fp.count + kLanes - 1) / kLanes;
+    const int64_t grid = (int64_t)tiles * n_work_curves;
+    pairs_kernel<R><<<(unsigned)grid, kThreads, 0, st>>>(cp, order, fp, t, K, r, rp, out);
+    return hipGetLastError();
+}
+template hipError_t launch_pairs<float>(hipStream_t, const CurveParams*, const int32_t*, int,
+                                        const FreqPlan&, const double*, const float*,
+                                        const float*, const float*, const PairOut&);
+template hipError_t launch_pairs<double>(hipStream_t, const CurveParams*, const int32_t*, int,
+                                         const FreqPlan&, const double*, const double*,
+                                         const double*, const double*, const PairOut&);
+
+hipError_t launch_peaks(hipStream_t st, const CurveParams* cp, int n_curves, const double* coarse,
+                        int n_coarse, double f0, double df, int top_k, int n_fine,
+                        const PeakOut& po) {
+    if (n_curves <= 0) return hipSuccess;
+    peaks_kernel<<<n_curves, kPeakBlock, 0, st>>>(cp, coarse, n_coarse, f0, df, top_k, n_fine,
+                                                   po);
+    return hipGetLastError();
+}
+
+hipError_t launch_best(hipStream_t st, const CurveParams* cp, int n_curves, const double* coarse,
+                       const double* coarse2, int n_coarse, const double* fine,
+                       const double* fine2, int top_k, int n_fine, int score_kind, double f0,
+                       double df, const PeakOut& po, DevResult* res) {
+    if (n_curves <= 0) return hipSuccess;
+    best_kernel<<<n_curves, kBestBlock, 0, st>>>(cp, coarse, coarse2, n_coarse, fine, fine2, top_k,
+                                                  n_fine, score_kind, f0, df, po, res);
+    return hipGetLastError();
+}
+
+}  // namespace qmi

@@ -1,0 +1,98 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every symbol include/qmi.h declares,
+its struct layouts match the header, and its host-only logic (the discriminator, argument
+validation) behaves as documented.  No GPU compute is called here."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1412_1840_amd import qmi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qmi.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*\*?\s*(qmi_\w+)\s*\(", text,
+                                 re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared_functions()
+    assert len(names) >= 14, names
+    L = qmi.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(names) == sorted(qmi.SYMBOLS)
+
+
+def test_header_constants_match_binding():
+    text = open(HEADER).read()
+
+    def val(name):
+        m = re.search(r"#define\s+%s\s+\(?(-?[0-9.]+)\)?" % name, text)
+        return float(m.group(1))
+
+    assert val("QMI_OK") == qmi.OK and val("QMI_EINVAL") == qmi.EINVAL
+    assert val("QMI_EAGAIN") == qmi.EAGAIN and val("QMI_EDEVICE") == qmi.EDEVICE
+    assert val("QMI_SIGMA_SILVERMAN") == qmi.SIGMA_SILVERMAN
+    assert val("QMI_SIGMA_MEDIAN_ERR") == qmi.SIGMA_MEDIAN_ERR
+    assert val("QMI_MAX_N") == qmi.MAX_N and val("QMI_MAX_TOPK") == qmi.MAX_TOPK
+    assert val("QMI_UNDECIDED") == qmi.UNDECIDED
+
+
+def test_struct_sizes():
+    assert ctypes.sizeof(qmi.Batch) == 40
+    assert ctypes.sizeof(qmi.KernelParams) == 24
+    assert ctypes.sizeof(qmi.Search) == 32
+    assert ctypes.sizeof(qmi.Thresholds) == 24
+    assert qmi.RESULT_DTYPE.itemsize == 96
+
+
+def test_discriminate_matches_oracle_rule():
+    rng = np.random.default_rng(3)
+    n = 500
+    res = np.zeros(n, qmi.RESULT_DTYPE)
+    res["score_qmi"] = rng.uniform(0, 1.5, n)
+    res["score_nckp"] = rng.uniform(0, 3, n)
+    res["psnr"] = rng.uniform(-1, 30, n)
+    res["status"] = np.where(rng.random(n) < 0.05, -4, 0)
+    res["score_qmi"][::37] = np.nan
+    res["psnr"][::41] = np.nan
+    edges = list(O.SNR_EDGES)
+    th = list(rng.uniform(0.2, 1.2, 8))
+    th[2] = res["score_qmi"][5]  # an exact tie must be "not periodic" (strict >)
+    for score, field in ((qmi.SCORE_QMI, "score_qmi"), (qmi.SCORE_NCKP, "score_nckp")):
+        got = qmi.discriminate(res, edges, th, score=score)
+        for k in range(n):
+            want = (O.UNDECIDED if res["status"][k] != 0 else
+                    O.discriminate(res[field][k], res["psnr"][k], th, edges))
+            assert got[k] == want, (k, res[k])
+    # caller-supplied pSNR overrides the result's
+    p = np.full(n, 3.0)
+    got = qmi.discriminate(res, edges, th, psnr=p)
+    ok = (res["status"] == 0) & np.isfinite(res["score_qmi"])
+    assert np.all(got[ok] == (res["score_qmi"][ok] > th[3]))
+
+
+def test_discriminate_rejects_bad_tables():
+    res = np.zeros(2, qmi.RESULT_DTYPE)
+    with pytest.raises(qmi.QMIError):
+        qmi.discriminate(res, [0.0, 2.0, 1.0], [0.1, 0.2])  # decreasing edges
+    with pytest.raises(ValueError):
+        qmi.discriminate(res, [0.0, 1.0], [0.1, 0.2])
+
+
+def test_create_without_device_fails_cleanly():
+    import torch
+
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a device is present")
+    with pytest.raises(qmi.QMIError) as ei:
+        qmi.Context(0)
+    assert ei.value.code == qmi.EDEVICE

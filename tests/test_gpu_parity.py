@@ -1,0 +1,293 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances (derived in the design doc from the arithmetic): the mixed-precision path evaluates each
+kernel value in FP32 (argument error ~ a few ulp of log2(e)/sigma_t^2, exp2 ~1 ulp) and sums short
+runs in FP32 before folding into FP64, so the three information potentials carry relative errors of
+order 1e-7; the score target is the per-frequency QMI relative error <= 1e-4, measured against
+max(|QMI_ref(f)|, 1e-3 max_f |QMI_ref|).  The FP64 path must agree to 1e-10.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1412_1840_amd import qmi, synth
+
+pytestmark = pytest.mark.gpu
+
+QMI_TOL = 1e-4
+V_RTOL = 2e-6
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    with qmi.Context(0) as c:
+        yield c
+
+
+def floor_rel(got, ref):
+    ref = np.asarray(ref)
+    den = np.maximum(np.abs(ref), 1e-3 * np.max(np.abs(ref)))
+    return np.abs(np.asarray(got) - ref) / den
+
+
+def pack(curves):
+    b = synth.pack(curves)
+    return b
+
+
+def oracle_ips(c, freqs, st=0.3, rule=O.SIGMA_SILVERMAN):
+    sy = O.sigma_y_of(c.y, c.e, rule)
+    return O.information_potentials(c.t, c.y, st, sy, freqs, mode=1)
+
+
+RAGGED_N = [2, 3, 37, 64, 255, 256, 257, 300, 513, 600]
+
+
+def test_periodogram_ragged_sizes(ctx):
+    curves = [synth.survey_batch_curve(k, n=n) for k, n in enumerate(RAGGED_N)]
+    b = pack(curves)
+    freqs = np.concatenate([[0.0, 1.0, 1 / 3.7], O.linear_grid(1e-3, 10.0, 297)])  # 300: 4 tiles + 44
+    sc, ips, ipy, st = ctx.periodogram(b.offsets, b.t, b.y, b.e, freqs, 0.3, want_ips=True)
+    assert np.all(st == 0)
+    worst = 0.0
+    for k, c in enumerate(curves):
+        ref = oracle_ips(c, freqs)
+        # IP_y sums the FP32-rounded Gram values in FP64: relative error ~ 2^-24 / sqrt(N^2).
+        np.testing.assert_allclose(ipy[k], ref.ipy, rtol=1e-7)
+        ev = [np.max(np.abs(ips[k, :, q] / r - 1)) for q, r in enumerate((ref.vj, ref.ipt, ref.vc))]
+        err = floor_rel(sc[k], O.qmi(ref))
+        print("N=%d V rel err %.2e %.2e %.2e  QMI floor-rel err max %.2e (f=0: %.2e abs)"
+              % (c.n, ev[0], ev[1], ev[2], err.max(), abs(sc[k, 0])))
+        worst = max(worst, err.max())
+    for k, c in enumerate(curves):
+        ref = oracle_ips(c, freqs)
+        np.testing.assert_allclose(ips[k, :, 0], ref.vj, rtol=V_RTOL)
+        np.testing.assert_allclose(ips[k, :, 1], ref.ipt, rtol=V_RTOL)
+        np.testing.assert_allclose(ips[k, :, 2], ref.vc, rtol=V_RTOL)
+        assert floor_rel(sc[k], O.qmi(ref)).max() <= QMI_TOL, c.n
+    print("worst QMI rel err %.3g" % worst)
+
+
+def test_nckp_score(ctx):
+    curves = [synth.survey_batch_curve(k, n=n) for k, n in enumerate([90, 400])]
+    b = pack(curves)
+    freqs = O.linear_grid(1e-3, 10.0, 130)
+    sc, _, _, st = ctx.periodogram(b.offsets, b.t, b.y, b.e, freqs, 0.3, score=qmi.SCORE_NCKP)
+    for k, c in enumerate(curves):
+        ref = O.nckp(oracle_ips(c, freqs))
+        # nCKP is a difference V_J - V_M: its absolute error is of order 1e-7 (V_J + V_M).
+        assert floor_rel(sc[k], ref).max() <= 1e-3
+
+
+@pytest.mark.parametrize("st_", [0.1, 0.6])
+def test_other_kernel_widths(ctx, st_):
+    curves = [synth.survey_batch_curve(k, n=n) for k, n in enumerate([150, 333])]
+    b = pack(curves)
+    freqs = O.linear_grid(1e-3, 10.0, 200)
+    sc, ips, _, _ = ctx.periodogram(b.offsets, b.t, b.y, b.e, freqs, st_, want_ips=True)
+    for k, c in enumerate(curves):
+        ref = oracle_ips(c, freqs, st=st_)
+        assert floor_rel(sc[k], O.qmi(ref)).max() <= QMI_TOL
+        np.testing.assert_allclose(ips[k, :, 2], ref.vc, rtol=5 * V_RTOL)
+
+
+def test_fp64_path(ctx):
+    curves = [synth.survey_batch_curve(k, n=n) for k, n in enumerate([5, 129, 300])]
+    b = pack(curves)
+    freqs = O.linear_grid(1e-3, 10.0, 100)
+    sc, ips, ipy, st = ctx.periodogram(b.offsets, b.t, b.y, b.e, freqs, 0.3,
+                                       precision=qmi.PREC_FP64, want_ips=True)
+    for k, c in enumerate(curves):
+        ref = oracle_ips(c, freqs)
+        # FP64 throughout: library exp/sincospi (~1 ulp) and a different summation order.
+        np.testing.assert_allclose(ips[k, :, 0], ref.vj, rtol=1e-11)
+        np.testing.assert_allclose(ips[k, :, 1], ref.ipt, rtol=1e-11)
+        np.testing.assert_allclose(ips[k, :, 2], ref.vc, rtol=1e-11)
+        assert floor_rel(sc[k], O.qmi(ref)).max() <= 1e-9
+
+
+def test_sigma_rules(ctx):
+    c = synth.survey_batch_curve(4, n=222)
+    b = pack([c])
+    freqs = O.linear_grid(1e-3, 10.0, 70)
+    for rule in (O.SIGMA_MEDIAN_ERR, 0.137):
+        sc, _, _, st = ctx.periodogram(b.offsets, b.t, b.y, b.e, freqs, 0.3, sigma_y=rule)
+        ref = oracle_ips(c, freqs, rule=rule)
+        assert floor_rel(sc[0], O.qmi(ref)).max() <= QMI_TOL
+
+
+def test_per_curve_status_and_neighbours(ctx):
+    good = synth.survey_batch_curve(1, n=120)
+    nan_t = synth.survey_batch_curve(2, n=50)
+    nan_t.t = nan_t.t.copy()
+    nan_t.t[7] = np.nan
+    flat = synth.survey_batch_curve(3, n=40)
+    flat.y = np.full(40, 17.0)
+    one = synth.survey_batch_curve(5, n=1)
+    empty = synth.Curve(np.zeros(0), np.zeros(0), np.zeros(0), False)
+    curves = [good, nan_t, flat, one, empty, good]
+    b = pack(curves)
+    freqs = O.linear_grid(1e-3, 10.0, 65)
+    sc, ips, ipy, st = ctx.periodogram(b.offsets, b.t, b.y, b.e, freqs, 0.3, want_ips=True)
+    assert list(st) == [0, qmi.EINVAL, qmi.EDEGENERATE, qmi.EINVAL, qmi.EINVAL, 0]
+    for k in (1, 2, 3, 4):
+        assert np.all(np.isnan(sc[k])) and np.isnan(ipy[k])
+    ref = O.qmi(oracle_ips(good, freqs))
+    assert floor_rel(sc[0], ref).max() <= QMI_TOL
+    assert np.array_equal(sc[0], sc[5])
+
+
+def test_call_level_errors_leave_outputs_untouched(ctx):
+    c = synth.survey_batch_curve(1, n=50)
+    b = pack([c])
+    out = np.full((1, 3), 7.0)
+    kp = qmi.kernel_params(-1.0)  # sigma_t <= 0
+    bb, off = ctx._batch(b.offsets, b.t, b.y, b.e)
+    f = np.array([0.1, 0.2, 0.3])
+    rc = qmi.lib().qmi_periodogram(ctx._h, bb, kp, f.ctypes.data, 3, 0, out.ctypes.data, None,
+                                   None, None)
+    assert rc == qmi.EINVAL and np.all(out == 7.0)
+    assert b"sigma_t" in qmi.lib().qmi_last_error(ctx._h)
+    with pytest.raises(qmi.QMIError):
+        ctx.best_period(b.offsets, b.t, b.y, b.e, 0.3, 1.0, 0.5, 100)  # f_max <= f_min
+    with pytest.raises(qmi.QMIError):
+        ctx.best_period(b.offsets, b.t, b.y, b.e, 0.3, 0.0, 1.0, 100, top_k=qmi.MAX_TOPK + 1)
+    with pytest.raises(qmi.QMIError):
+        ctx.periodogram(b.offsets, b.t, b.y, None, f, 0.3, sigma_y=qmi.SIGMA_MEDIAN_ERR)
+    res, _ = ctx.best_period([0], np.zeros(0), np.zeros(0), None, 0.3, 0.0, 1.0, 10)
+    assert len(res) == 0
+
+
+def test_sample_order_and_batch_composition(ctx):
+    c = synth.survey_batch_curve(6, n=301)
+    p = np.random.default_rng(0).permutation(c.n)
+    cp = synth.Curve(c.t[p], c.y[p], c.e[p], c.periodic)
+    freqs = O.linear_grid(1e-3, 10.0, 128)
+    alone, _, _, _ = ctx.periodogram([0, c.n], c.t, c.y, c.e, freqs, 0.3)
+    perm, _, _, _ = ctx.periodogram([0, c.n], cp.t, cp.y, cp.e, freqs, 0.3)
+    assert floor_rel(perm[0], alone[0]).max() <= 2 * QMI_TOL
+    others = [synth.survey_batch_curve(k, n=n) for k, n in ((10, 900), (11, 77), (12, 513))]
+    b = pack([others[0], c, others[1], others[2]])
+    mixed, _, _, _ = ctx.periodogram(b.offsets, b.t, b.y, b.e, freqs, 0.3)
+    assert np.array_equal(mixed[1], alone[0])  # bitwise: per-curve work is batch independent
+
+
+SEARCH = dict(f_min=1e-3, f_max=10.0, n_coarse=400, top_k=5, n_fine=50)
+
+
+def _near_tie(ref: O.SearchResult) -> bool:
+    q = np.sort(ref.fine_scores.ravel())[::-1] if ref.fine_scores is not None else None
+    return q is not None and len(q) > 1 and (q[0] - q[1]) <= 1e-6 * abs(q[0])
+
+
+def test_best_period_parity(ctx):
+    curves = [synth.survey_batch_curve(k, n=n) for k, n in
+              enumerate([60, 97, 128, 200, 257, 311, 380, 400])]
+    b = pack(curves)
+    res, coarse = ctx.best_period(b.offsets, b.t, b.y, b.e, 0.3, want_coarse=True, **SEARCH)
+    mism = []
+    for k, c in enumerate(curves):
+        ref = O.best_period(c.t, c.y, c.e, 0.3, O.SIGMA_SILVERMAN, **SEARCH)
+        r = res[k]
+        assert r["status"] == 0
+        assert floor_rel(coarse[k], ref.coarse_scores).max() <= QMI_TOL
+        assert r["sigma_y"] == pytest.approx(ref.sigma_y, rel=1e-13)
+        assert r["n_peaks"] == ref.n_peaks
+        same = (r["coarse_argmax"] == ref.coarse_argmax and r["coarse_index"] == ref.coarse_index
+                and r["peak_rank"] == ref.peak_rank and r["fine_index"] == ref.fine_index)
+        if not same:
+            mism.append((k, _near_tie(ref)))
+            continue
+        assert r["f_best"] == ref.f_best  # same index -> the same FP64 grid point
+        assert abs(r["score"] - ref.score) <= QMI_TOL * abs(ref.score)
+        assert abs(r["score_nckp"] - ref.nckp) <= 1e-3 * abs(ref.nckp) + 1e-9
+        assert r["period"] == pytest.approx(1.0 / ref.f_best, rel=1e-15)
+    assert all(tie for _, tie in mism), mism
+
+
+def test_best_period_without_refinement_and_nckp_search(ctx):
+    c = synth.single_sinusoid()
+    kw = dict(f_min=1e-3, f_max=10.0, n_coarse=1500, top_k=0, n_fine=0)
+    res, _ = ctx.best_period([0, c.n], c.t, c.y, c.e, 0.3, **kw)
+    ref = O.best_period(c.t, c.y, c.e, 0.3, O.SIGMA_SILVERMAN, **kw)
+    assert res[0]["coarse_argmax"] == ref.coarse_argmax and res[0]["peak_rank"] == -1
+    assert res[0]["f_best"] == ref.f_best
+    kw = dict(f_min=1e-3, f_max=2.0, n_coarse=300, top_k=3, n_fine=40, score=O.SCORE_NCKP)
+    res, _ = ctx.best_period([0, c.n], c.t, c.y, c.e, 0.3, **kw)
+    ref = O.best_period(c.t, c.y, c.e, 0.3, O.SIGMA_SILVERMAN, **kw)
+    assert res[0]["coarse_index"] == ref.coarse_index and res[0]["fine_index"] == ref.fine_index
+
+
+def test_full_size_survey_curve_sampled(ctx):
+    """A survey-batch curve at full size (N = 1000, 20k coarse + 10 x 1000 fine, the launch the
+    benchmark times): sampled coarse scores against the oracle, and the peak/best logic of the
+    oracle applied to the GPU's own coarse scores."""
+    c = synth.survey_batch_curve(2, n=1000)
+    kw = synth.WORKLOADS["survey_batch"]
+    args = dict(f_min=kw["f_min"], f_max=kw["f_max"], n_coarse=kw["n_coarse"], top_k=kw["top_k"],
+                n_fine=kw["n_fine"])
+    res, coarse = ctx.best_period([0, c.n], c.t, c.y, c.e, 0.3, want_coarse=True, **args)
+    r = res[0]
+    grid = O.linear_grid(args["f_min"], args["f_max"], args["n_coarse"])
+    idx = np.unique(np.concatenate([np.random.default_rng(1).integers(0, len(grid), 40),
+                                    [0, len(grid) - 1, r["coarse_argmax"]]]))
+    ref = O.qmi(oracle_ips(c, grid[idx]))
+    assert floor_rel(coarse[0, idx], ref).max() <= QMI_TOL
+    peaks = O.top_peaks(coarse[0], args["top_k"])
+    assert r["n_peaks"] == len(peaks)
+    assert r["coarse_index"] == peaks[r["peak_rank"]]
+    assert r["coarse_argmax"] == int(np.argmax(coarse[0]))
+    lo, hi = O.fine_window(grid, int(r["coarse_index"]))
+    f_expect = O.linear_grid(lo, hi, args["n_fine"])[r["fine_index"]]
+    assert r["f_best"] == f_expect
+    q = O.qmi(oracle_ips(c, [r["f_best"]]))[0]
+    assert abs(r["score"] - q) <= QMI_TOL * abs(q)
+
+
+def test_long_baseline_high_frequency_fold(ctx):
+    """7000-day baseline at frequencies up to 20 / day: f t reaches 1.4e5 cycles, the FP64 fold
+    must keep the phase exact enough for the same 1e-4 QMI bar."""
+    c = synth.long_baseline_curve(0)
+    freqs = np.concatenate([O.linear_grid(19.5, 20.0, 96), O.linear_grid(1e-3, 20.0, 64)])
+    sc, _, _, _ = ctx.periodogram([0, c.n], c.t, c.y, c.e, freqs, 0.3)
+    ref = O.qmi(oracle_ips(c, freqs))
+    assert floor_rel(sc[0], ref).max() <= QMI_TOL
+
+
+def test_maximum_length(ctx):
+    rng = np.random.default_rng(9)
+    n = qmi.MAX_N
+    t = np.sort(rng.uniform(0, 2500, n))
+    y = 0.2 * np.sin(2 * np.pi * t / 1.37) + rng.normal(0, 0.1, n)
+    freqs = np.array([1 / 1.37, 0.01, 3.3])
+    sc, _, _, st = ctx.periodogram([0, n], t, y, None, freqs, 0.3)
+    assert st[0] == 0
+    ref = O.qmi(O.information_potentials(t, y, 0.3, O.silverman_sigma(y), freqs))
+    assert floor_rel(sc[0], ref).max() <= QMI_TOL
+    t2 = np.concatenate([t, [2600.0]])
+    y2 = np.concatenate([y, [0.0]])
+    sc2, _, _, st2 = ctx.periodogram([0, n + 1], t2, y2, None, freqs, 0.3)
+    assert st2[0] == qmi.EINVAL and np.all(np.isnan(sc2[0]))
+
+
+def test_device_pointer_variants(ctx):
+    import torch
+
+    curves = [synth.survey_batch_curve(k, n=n) for k, n in enumerate([90, 260, 41])]
+    b = pack(curves)
+    freqs = O.linear_grid(1e-3, 10.0, 150)
+    host, _, _, _ = ctx.periodogram(b.offsets, b.t, b.y, b.e, freqs, 0.3)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    T, Y, E, Fq = dev(b.t), dev(b.y), dev(b.e), dev(freqs)
+    out = torch.empty((b.n_curves, len(freqs)), dtype=torch.float64, device="cuda")
+    ctx.periodogram_dev(b.offsets, T, Y, E, Fq, out, 0.3)
+    assert np.array_equal(out.cpu().numpy(), host)
+    res_h, coarse_h = ctx.best_period(b.offsets, b.t, b.y, b.e, 0.3, want_coarse=True, **SEARCH)
+    cd = torch.empty((b.n_curves, SEARCH["n_coarse"]), dtype=torch.float64, device="cuda")
+    res_d = ctx.best_period_dev(b.offsets, T, Y, E, 0.3, coarse_out=cd, **SEARCH)
+    assert np.array_equal(res_d, res_h)
+    assert np.array_equal(cd.cpu().numpy(), coarse_h)
+    st = ctx.stats()
+    assert st["pair_launches"] == 2 and st["pair_kernel_ms"] > 0 and st["pair_items"] > 0
