@@ -20,10 +20,11 @@ import numpy as np  # noqa: E402
 
 METRIC = "lightcurves/sec (N~600, 20k freqs) vs plain; Gpairs/s % VALU peak; p99 ms"
 
-# VALU roofline of the pair sums (derived from unit counts): each pair x frequency
-# item needs 5 FP32 VALU operations and one v_exp_f32 at a quarter of the FP32 rate (4 slots):
-# 256 CUs x 64 FP32 lanes x 2.4 GHz / 9 slots.
-PEAK_ITEMS_PER_S = 256 * 64 * 2.4e9 / 9.0
+# VALU roofline of the pair sums, from unit counts: each pair x frequency item needs 6 FP32 VALU
+# operations (a multiply and two FMAs for the squared half-angle sine, two adds and an FMA for the
+# three accumulations) and one v_exp_f32, which issues at half the FP32 rate (2 slots) on gfx950:
+# 256 CUs x 64 FP32 lanes x 2.4 GHz / 8 slots.  The valu_rates probe measures the same body.
+PEAK_ITEMS_PER_S = 256 * 64 * 2.4e9 / 8.0
 
 
 def parse():
@@ -38,7 +39,78 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=8,
                     help="curves of the CPU-oracle baseline sample (0: skip)")
     ap.add_argument("--cpu-freqs", type=int, default=512)
+    ap.add_argument("--no-probe", action="store_true", help="skip the VALU rate probe")
+    ap.add_argument("--serve-requests", type=int, default=1000,
+                    help="requests of the serving measurement (0: skip)")
+    ap.add_argument("--serve-load", type=float, default=0.5,
+                    help="Poisson arrival rate as a fraction of the measured batch throughput")
+    ap.add_argument("--serve-batch", type=int, default=64)
+    ap.add_argument("--serve-inflight", type=int, default=3)
     return ap.parse_args()
+
+
+def serving(qmi, synth, wl, st_, rate, n_req, max_batch, inflight):
+    """Poisson stream of single-curve requests (serving-stream lengths, survey mix and search)
+    into the continuous-batching loop; latency = completion (poll) - arrival, host clock."""
+    import threading
+
+    curves = [synth.serving_curve(k) for k in range(n_req)]
+    arrivals = synth.poisson_arrivals(0, n_req, rate)
+    ctx = qmi.Context(0)
+    kw = dict(f_min=wl["f_min"], f_max=wl["f_max"], n_coarse=wl["n_coarse"], top_k=wl["top_k"],
+              n_fine=wl["n_fine"])
+    ctx.serve_start(st_, max_batch=max_batch, max_inflight=inflight, **kw)
+    t_arr = np.zeros(n_req)
+    t_done = np.full(n_req, np.nan)
+    status = np.zeros(n_req, np.int32)
+    t0 = time.perf_counter()
+
+    def submitter():
+        for k, c in enumerate(curves):
+            delay = t0 + arrivals[k] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            t_arr[k] = time.perf_counter()
+            while not ctx.submit(c.t, c.y, c.e, tag=k):
+                time.sleep(0.0005)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    got = 0
+    deadline = t0 + arrivals[-1] + 120.0
+    while got < n_req and time.perf_counter() < deadline:
+        res, tags = ctx.poll(256, 2000)
+        now = time.perf_counter()
+        for r, tg in zip(res, tags):
+            t_done[int(tg)] = now
+            status[int(tg)] = r["status"]
+        got += len(tags)
+    th.join()
+    ctx.serve_stop()
+    ctx.close()
+    lat = (t_done - t_arr) * 1e3
+    ok = np.isfinite(lat)
+    span = np.nanmax(t_done) - t0
+    return {"requests": n_req, "completed": int(ok.sum()), "arrival_rate_per_s": rate,
+            "p50_ms": float(np.percentile(lat[ok], 50)), "p99_ms": float(np.percentile(lat[ok], 99)),
+            "max_ms": float(np.max(lat[ok])), "throughput_per_s": float(ok.sum() / span),
+            "max_batch": max_batch, "max_inflight": inflight,
+            "lengths": "round(lognormal(ln 500, 0.5)) in [50, 2000]",
+            "bad_status": int(np.sum(status != 0))}
+
+
+def valu_probe():
+    import subprocess
+
+    exe = os.path.join(ROOT, "paper_1412_1840_amd", "valu_rates")
+    if not os.path.exists(exe):
+        return None
+    try:
+        out = subprocess.run([exe], stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True,
+                             timeout=120)
+        return json.loads(out.stdout.strip().splitlines()[-1]) if out.returncode == 0 else None
+    except Exception:
+        return None
 
 
 def main():
@@ -47,6 +119,7 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d "
               "requested)" % a.gpus, file=sys.stderr)
         sys.exit(2)
+    probe = None if a.no_probe else valu_probe()
     import torch
 
     from paper_1412_1840_amd import qmi, synth
@@ -125,6 +198,11 @@ def main():
                          "the workload needs" % (len(cs), len(fr), citems, cdt, citems / cdt,
                                                  items_per_curve)}
 
+    serve = None
+    if a.serve_requests > 0:
+        serve = serving(qmi, synth, wl, st_, a.serve_load * value, a.serve_requests,
+                        a.serve_batch, a.serve_inflight)
+
     line = {
         "metric": METRIC,
         "value": value,
@@ -148,8 +226,13 @@ def main():
                      "unit": "G pair*freq items/s", "frac": achieved / PEAK_ITEMS_PER_S,
                      "traffic": None,
                      "kernel": "pairs_kernel<float>", "launches": launches,
-                     "avg_launch_ms": pair_ms / max(launches, 1)},
+                     "avg_launch_ms": pair_ms / max(launches, 1),
+                     "probe_pair_items_per_s": probe and probe.get("pair_items_per_s"),
+                     "probe_exp_per_s": probe and probe.get("exp_per_s"),
+                     "probe_fma_per_s": probe and probe.get("fma_per_s")},
         "plain": plain,
+        "serving": serve,
+        "p99_ms": serve and serve["p99_ms"],
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

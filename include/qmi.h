@@ -220,6 +220,19 @@ int qmi_discriminate(const qmi_result *best, int32_t n_curves, const double *psn
                      const qmi_thresholds *th, uint8_t *is_periodic);
 
 /*
+ * Threshold calibration (Sec. 4.1): for each SNR bin b = [edges[b], edges[b+1]), over the curves k
+ * with psnr[k] in the bin and a finite score, sweep n_points thresholds evenly spaced on
+ * [min score, max score] (th_j = min + j * ((max - min) / (n_points - 1))), label a curve periodic
+ * iff score > th_j, and keep the threshold of the highest F1 = 2 p r / (p + r) against truth[k]
+ * (1 periodic, 0 not); ties go to the lowest threshold.  A bin with no periodic member gets
+ * th = max score and F1 = p = r = 0; an empty bin th = +inf.  Outputs are [n_bins] host arrays
+ * (f1_out, precision_out, recall_out nullable).  Host-only; returns QMI_EINVAL on bad arguments.
+ */
+int qmi_calibrate(const double *scores, const double *psnr, const uint8_t *truth, int32_t n,
+                  const double *edges, int32_t n_bins, int32_t n_points, double *th_out,
+                  double *f1_out, double *precision_out, double *recall_out);
+
+/*
  * Serving (continuous batching).  qmi_submit copies one curve (host arrays of n samples) into
  * library-owned pinned staging and queues it with a caller tag; it returns QMI_EAGAIN when the
  * admission budget (queued plus in-flight device memory) is full.  A background host thread admits

@@ -53,7 +53,7 @@ struct qmi_ctx {
     int ev_used = 0;
     // Device buffers, grown on demand.
     enum {
-        kT, kY, kE, kCP, kOrder, kRowStart, kK, kR, kRP, kRD, kCoarse, kCoarse2, kFine, kFine2,
+        kT, kY, kE, kCP, kOrder, kRowStart, kK, kR, kRP, kRD, kKS, kCoarse, kCoarse2, kFine, kFine2,
         kIps, kPeakK, kNpk, kWin, kArgmax, kRes, kFreqs, kStatusDummy, kNumBufs
     };
     Buf bufs[kNumBufs];
@@ -61,6 +61,8 @@ struct qmi_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     std::vector<uint64_t> graph_key;
+    int graph_ev_used = 0;
+    std::vector<int32_t> graph_pair_ev;
     // Serving.
     struct Serve;
     std::unique_ptr<Serve> serve;
@@ -197,6 +199,7 @@ size_t curve_bytes(int64_t n, int64_t F1, int64_t F2, bool fp64, bool ips, bool 
     b += (size_t)n * (size_t)npad * rs;          // K
     b += (size_t)n * rs + (size_t)npad * rs;     // r, rp
     b += (size_t)n * 8;                          // rd
+    b += (size_t)((n + 8 * (fp64 ? 16 : 32) - 1) / (8 * (fp64 ? 16 : 32))) * 8 * n * rs;  // ks
     b += sizeof(CurveParams) + 64;
     b += (size_t)F1 * 8 * (two_scores ? 2 : 1);  // coarse / periodogram scores
     b += (size_t)F2 * 8 * 2;                     // fine scores
@@ -280,7 +283,8 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
     std::vector<CurveParams> cp(nc);
     std::vector<int32_t> order(nc);
     std::vector<int64_t> row_start(nc);
-    int64_t koff = 0, poff = 0, rows = 0;
+    int64_t koff = 0, poff = 0, ksoff = 0, rows = 0;
+    constexpr int kPassR = kWaves * rows_per_wave<R>();
     int max_n = 2;
     for (int32_t i = 0; i < nc; ++i) {
         const int32_t k = g.c0 + i;
@@ -298,8 +302,10 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
             p.npad = (int32_t)round_up(p.n, kPass);
             p.koff = koff;
             p.poff = poff;
+            p.ksoff = ksoff;
             koff += (int64_t)p.n * p.npad;
             poff += p.npad;
+            ksoff += (int64_t)((p.n + kPassR - 1) / kPassR) * kWaves * p.n;
             row_start[i] = rows;
             rows += p.n;
             max_n = std::max(max_n, p.n);
@@ -336,6 +342,7 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
     ENSURE(qmi_ctx::kR, std::max<int64_t>(ns, 1) * sizeof(R));
     ENSURE(qmi_ctx::kRP, std::max<int64_t>(poff, 1) * sizeof(R));
     ENSURE(qmi_ctx::kRD, std::max<int64_t>(ns, 1) * 8);
+    ENSURE(qmi_ctx::kKS, std::max<int64_t>(ksoff, 1) * sizeof(R));
     if (!(cs.periodogram && cs.dev_outputs)) ENSURE(qmi_ctx::kCoarse, nc * F1 * 8);
     if (!cs.periodogram) ENSURE(qmi_ctx::kCoarse2, nc * F1 * 8);
     if (refine) {
@@ -384,11 +391,7 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
     R* r = dptr<R>(ctx, qmi_ctx::kR);
     R* rp = dptr<R>(ctx, qmi_ctx::kRP);
     double* rd = dptr<double>(ctx, qmi_ctx::kRD);
-
-    record(ctx);  // device section start
-    HIP_OK(ctx, launch_prologue(st, dcp, nc, max_n, t, y, e));
-    HIP_OK(ctx, launch_gram<R>(st, dcp, nc, rows, drow, y, K, r, rp, rd));
-    HIP_OK(ctx, launch_gram_finalize<R>(st, dcp, nc, rd, rp));
+    R* ks = dptr<R>(ctx, qmi_ctx::kKS);
 
     FreqPlan fp{};
     PairOut po{};
@@ -419,40 +422,123 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
         po.ips = nullptr;
         po.score_kind = score_kind;
     }
-    pair_event_idx.push_back(ctx->ev_used);
-    record(ctx);
-    HIP_OK(ctx, launch_pairs<R>(st, dcp, dorder, nc, fp, t, K, r, rp, po));
-    record(ctx);
-
+    PeakOut pk{};
+    double* fine = nullptr;
+    double* fine2 = nullptr;
+    FreqPlan ff{};
     if (!cs.periodogram) {
-        const qmi_search* s = cs.search;
-        PeakOut pk{dptr<int32_t>(ctx, qmi_ctx::kPeakK), dptr<int32_t>(ctx, qmi_ctx::kNpk),
-                   dptr<double>(ctx, qmi_ctx::kWin), dptr<int32_t>(ctx, qmi_ctx::kArgmax)};
-        HIP_OK(ctx, launch_peaks(st, dcp, nc, coarse, s->n_coarse, fp.f0, fp.df, top_k,
-                                 std::max(n_fine, 2), pk));
-        double* fine = nullptr;
-        double* fine2 = nullptr;
+        pk = PeakOut{dptr<int32_t>(ctx, qmi_ctx::kPeakK), dptr<int32_t>(ctx, qmi_ctx::kNpk),
+                     dptr<double>(ctx, qmi_ctx::kWin), dptr<int32_t>(ctx, qmi_ctx::kArgmax)};
         if (refine) {
             fine = dptr<double>(ctx, qmi_ctx::kFine);
             fine2 = dptr<double>(ctx, qmi_ctx::kFine2);
-            FreqPlan ff{};
             ff.kind = 2;
             ff.count = (int32_t)F2;
             ff.n_fine = n_fine;
             ff.top_k = top_k;
             ff.win = pk.win;
             ff.npk = pk.npk;
-            PairOut fo{fine, fine2, nullptr, score_kind, 0};
-            pair_event_idx.push_back(ctx->ev_used);
-            record(ctx);
-            HIP_OK(ctx, launch_pairs<R>(st, dcp, dorder, nc, ff, t, K, r, rp, fo));
-            record(ctx);
         }
-        HIP_OK(ctx, launch_best(st, dcp, nc, coarse, coarse2, s->n_coarse, fine, fine2,
-                                refine ? top_k : 0, refine ? n_fine : 0, score_kind, fp.f0,
-                                fp.df, pk, dptr<DevResult>(ctx, qmi_ctx::kRes)));
     }
-    record(ctx);  // device section end
+    DevResult* dres = cs.periodogram ? nullptr : dptr<DevResult>(ctx, qmi_ctx::kRes);
+
+    // The device section: every kernel of the call, and the timing events around the pair kernels.
+    // It contains no copies or allocations, so it can be captured into a hipGraph and replayed.
+    auto section = [&]() -> int {
+        record(ctx);  // device section start
+        HIP_OK(ctx, launch_prologue(st, dcp, nc, max_n, t, y, e));
+        HIP_OK(ctx, launch_gram<R>(st, dcp, nc, rows, drow, y, K, r, rp, rd));
+        HIP_OK(ctx, launch_gram_finalize<R>(st, dcp, nc, rd, rp));
+        HIP_OK(ctx, launch_ksum<R>(st, dcp, nc, K, ks));
+        pair_event_idx.push_back(ctx->ev_used);
+        record(ctx);
+        HIP_OK(ctx, launch_pairs<R>(st, dcp, dorder, nc, fp, t, K, r, rp, ks, po));
+        record(ctx);
+        if (!cs.periodogram) {
+            const qmi_search* s = cs.search;
+            HIP_OK(ctx, launch_peaks(st, dcp, nc, coarse, s->n_coarse, fp.f0, fp.df, top_k,
+                                     std::max(n_fine, 2), pk));
+            if (refine) {
+                PairOut fo{fine, fine2, nullptr, score_kind, 0};
+                pair_event_idx.push_back(ctx->ev_used);
+                record(ctx);
+                HIP_OK(ctx, launch_pairs<R>(st, dcp, dorder, nc, ff, t, K, r, rp, ks, fo));
+                record(ctx);
+            }
+            HIP_OK(ctx, launch_best(st, dcp, nc, coarse, coarse2, s->n_coarse, fine, fine2,
+                                    refine ? top_k : 0, refine ? n_fine : 0, score_kind, fp.f0,
+                                    fp.df, pk, dres));
+        }
+        record(ctx);  // device section end
+        return QMI_OK;
+    };
+
+    // Graph replay: only for a call that is one group (event indices then start at 0).
+    bool ran = false;
+    if (ctx->use_graph && ctx->ev_used == 0) {
+        auto u = [](const void* p) { return (uint64_t)(uintptr_t)p; };
+        auto dbits = [](double v) { uint64_t b; std::memcpy(&b, &v, 8); return b; };
+        std::vector<uint64_t> key = {
+            (uint64_t)fp64, (uint64_t)cs.periodogram, (uint64_t)nc, (uint64_t)rows,
+            (uint64_t)max_n, (uint64_t)F1, (uint64_t)F2, (uint64_t)top_k, (uint64_t)n_fine,
+            (uint64_t)score_kind, dbits(fp.f0), dbits(fp.df), u(st), u(t), u(y), u(e), u(dcp),
+            u(dorder), u(drow), u(K), u(r), u(rp), u(rd), u(ks), u(dfreqs), u(coarse), u(coarse2),
+            u(po.ips), u(fine), u(fine2), u(pk.peak_k), u(pk.npk), u(pk.win), u(pk.argmax),
+            u(dres)};
+        if (ctx->graph_exec && key == ctx->graph_key) {
+            HIP_OK(ctx, hipGraphLaunch(ctx->graph_exec, st));
+            ctx->ev_used = ctx->graph_ev_used;
+            pair_event_idx = ctx->graph_pair_ev;
+            ran = true;
+            ctx->stats.used_graph = 1;
+        } else {
+            if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+            if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+            ctx->graph_exec = nullptr;
+            ctx->graph = nullptr;
+            ctx->graph_key.clear();
+            // Event objects must exist before capture starts (creation is not a stream operation,
+            // but keep the captured section free of anything but launches and records).
+            while ((int)ctx->ev.size() < 8) {
+                hipEvent_t ev;
+                HIP_OK(ctx, hipEventCreate(&ev));
+                ctx->ev.push_back(ev);
+            }
+            bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            if (ok) {
+                const int rc_sec = section();
+                hipGraph_t graph = nullptr;
+                const bool ended = hipStreamEndCapture(st, &graph) == hipSuccess;
+                hipGraphExec_t exec = nullptr;
+                ok = rc_sec == QMI_OK && ended && graph &&
+                     hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+                if (ok) {
+                    ctx->graph = graph;
+                    ctx->graph_exec = exec;
+                    ctx->graph_key = key;
+                    ctx->graph_ev_used = ctx->ev_used;
+                    ctx->graph_pair_ev = pair_event_idx;
+                    HIP_OK(ctx, hipGraphLaunch(exec, st));
+                    ran = true;
+                    ctx->stats.used_graph = 1;
+                } else {
+                    if (graph) (void)hipGraphDestroy(graph);
+                    (void)hipGetLastError();
+                    ctx->use_graph = false;  // this runtime cannot capture the section: run eagerly
+                    ctx->ev_used = 0;
+                    pair_event_idx.clear();
+                    ctx->err.clear();
+                }
+            } else {
+                (void)hipGetLastError();
+                ctx->use_graph = false;
+            }
+        }
+    }
+    if (!ran) {
+        const int rc_sec = section();
+        if (rc_sec != QMI_OK) return rc_sec;
+    }
 
     // Results back to the caller.
     if (cs.periodogram) {
@@ -590,7 +676,6 @@ int run_call(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs) {
     if (ctx->ev_used >= 2 &&
         hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[ctx->ev_used - 1]) == hipSuccess)
         ctx->stats.device_ms = ms;
-    ctx->stats.used_graph = 0;
     return QMI_OK;
 }
 
@@ -873,6 +958,73 @@ int qmi_discriminate(const qmi_result* best, int32_t n_curves, const double* psn
                 }
         }
         is_periodic[k] = v;
+    }
+    return QMI_OK;
+}
+
+int qmi_calibrate(const double* scores, const double* psnr, const uint8_t* truth, int32_t n,
+                  const double* edges, int32_t n_bins, int32_t n_points, double* th_out,
+                  double* f1_out, double* precision_out, double* recall_out) {
+    if (n < 0 || n_bins < 1 || n_points < 1 || !edges || !th_out) return QMI_EINVAL;
+    if (n > 0 && (!scores || !psnr || !truth)) return QMI_EINVAL;
+    for (int32_t b = 0; b < n_bins; ++b)
+        if (!(edges[b] <= edges[b + 1])) return QMI_EINVAL;
+    std::vector<double> s;
+    std::vector<uint8_t> lab;
+    for (int32_t b = 0; b < n_bins; ++b) {
+        s.clear();
+        lab.clear();
+        for (int32_t k = 0; k < n; ++k) {
+            const double p = psnr[k];
+            if (edges[b] <= p && p < edges[b + 1] && scores[k] == scores[k]) {
+                s.push_back(scores[k]);
+                lab.push_back(truth[k] ? 1 : 0);
+            }
+        }
+        double th = INFINITY, f1 = 0.0, pr = 0.0, rc = 0.0;
+        if (!s.empty()) {
+            const double lo = *std::min_element(s.begin(), s.end());
+            const double hi = *std::max_element(s.begin(), s.end());
+            int64_t pos = 0;
+            for (uint8_t v : lab) pos += v;
+            if (pos == 0) {
+                th = hi;
+            } else {
+                // Sort by score so each threshold's counts come from one pointer sweep.
+                std::vector<size_t> idx(s.size());
+                for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
+                std::sort(idx.begin(), idx.end(), [&](size_t a, size_t c) { return s[a] < s[c]; });
+                const double step = n_points > 1 ? (hi - lo) / (double)(n_points - 1) : 0.0;
+                size_t below = 0;       // curves with score <= threshold
+                int64_t pos_below = 0;  // periodic curves among them
+                bool have = false;
+                for (int32_t j = 0; j < n_points; ++j) {
+                    const double c = n_points > 1 ? lo + (double)j * step : lo;
+                    while (below < idx.size() && s[idx[below]] <= c) {
+                        pos_below += lab[idx[below]];
+                        ++below;
+                    }
+                    const int64_t tp = pos - pos_below;
+                    const int64_t fp = (int64_t)(idx.size() - below) - tp;
+                    const int64_t fn = pos_below;
+                    const double p = (tp + fp) ? (double)tp / (double)(tp + fp) : 0.0;
+                    const double r = (tp + fn) ? (double)tp / (double)(tp + fn) : 0.0;
+                    const double den = 1.0 * p + r;
+                    const double f = den == 0.0 ? 0.0 : 2.0 * p * r / den;
+                    if (!have || f > f1) {
+                        have = true;
+                        f1 = f;
+                        th = c;
+                        pr = p;
+                        rc = r;
+                    }
+                }
+            }
+        }
+        th_out[b] = th;
+        if (f1_out) f1_out[b] = f1;
+        if (precision_out) precision_out[b] = pr;
+        if (recall_out) recall_out[b] = rc;
     }
     return QMI_OK;
 }

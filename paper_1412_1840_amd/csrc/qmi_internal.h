@@ -36,6 +36,7 @@ struct CurveParams {
     int64_t off;   // first sample in the packed t / y / e arrays
     int64_t koff;  // first element of this curve's K table
     int64_t poff;  // first element of this curve's permuted row-sum array (npad entries)
+    int64_t ksoff; // first element of this curve's column K-sum table (passes * kWaves * n)
     int32_t n;     // samples
     int32_t npad;  // K-table row length (multiple of kPass)
     int32_t status;
@@ -47,7 +48,16 @@ struct CurveParams {
     double ipy;    // IP_y
     double rsum;   // sum_i r_i
     double psnr;
+    double bk;     // diagonal value of the stored K table (B rounded to the kernel type)
+    double sjc;    // sum_{i<j} K(i,j)            (FP64, from the stored K table)
+    double scc;    // sum_{i<j} (r_i + r_j) = (N-1) sum_i r_i
 };
+
+// Rows per wave of the pair kernel for each arithmetic type (a pass is kWaves times this).
+template <typename R>
+constexpr int rows_per_wave() {
+    return sizeof(R) == 4 ? 32 : 16;
+}
 
 // How frequency slot s of curve c maps to a frequency.
 struct FreqPlan {
@@ -93,9 +103,11 @@ template <typename R>
 hipError_t launch_gram_finalize(hipStream_t st, CurveParams* cp, int n_curves, const double* rd,
                                 R* rp);
 template <typename R>
+hipError_t launch_ksum(hipStream_t st, const CurveParams* cp, int n_curves, const R* K, R* ks);
+template <typename R>
 hipError_t launch_pairs(hipStream_t st, const CurveParams* cp, const int32_t* order,
                         int n_work_curves, const FreqPlan& fp, const double* t, const R* K,
-                        const R* r, const R* rp, const PairOut& out);
+                        const R* r, const R* rp, const R* ks, const PairOut& out);
 hipError_t launch_peaks(hipStream_t st, const CurveParams* cp, int n_curves, const double* coarse,
                         int n_coarse, double f0, double df, int top_k, int n_fine,
                         const PeakOut& po);

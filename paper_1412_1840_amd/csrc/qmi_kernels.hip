@@ -226,8 +226,45 @@ gram_finalize_kernel(CurveParams* __restrict__ cp, const double* __restrict__ rd
     for (int i = threadIdx.x; i < P.n; i += kFinBlock) acc += rd[P.off + i];
     acc = block_sum<kFinBlock>(acc, red);
     if (threadIdx.x == 0) {
+        const double N = (double)P.n;
+        const double bk = (double)(R)P.B;  // K(i,i) as stored
         cp[c].rsum = acc;
-        cp[c].ipy = acc / ((double)P.n * (double)P.n);
+        cp[c].ipy = acc / (N * N);
+        cp[c].bk = bk;
+        cp[c].sjc = 0.5 * (acc - N * bk);  // the table is symmetric: sum_{i<j} K = (sum - diag)/2
+        cp[c].scc = (N - 1.0) * acc;
+    }
+}
+
+// Column K-sums in the pair kernel's own rounding order: for pass p, wave w and column j, the
+// sum over the wave's rows i < j of K(i, j), accumulated in the kernel type row by row exactly as
+// the pair kernel accumulates K(i, j) g_ij.  Where every g_ij of a column is exactly 1 (coincident
+// phases, f = 0) the kernel's column sum equals this value bit for bit, so their difference is
+// exactly zero.  One block per curve.
+constexpr int kKsBlock = 256;
+
+template <typename R>
+__global__ void __launch_bounds__(kKsBlock)
+ksum_kernel(const CurveParams* __restrict__ cp, const R* __restrict__ K, R* __restrict__ ks) {
+    constexpr int ROWS = rows_per_wave<R>();
+    constexpr int PASS = kWaves * ROWS;
+    const int c = blockIdx.x;
+    const CurveParams P = cp[c];
+    if (P.status != 0 || P.npad == 0) return;
+    const int n = P.n;
+    const int passes = (n + PASS - 1) / PASS;
+    const int64_t total = (int64_t)passes * kWaves * n;
+    for (int64_t e = threadIdx.x; e < total; e += kKsBlock) {
+        const int j = (int)(e % n);
+        const int pw = (int)(e / n);
+        const int w = pw % kWaves, base = (pw / kWaves) * PASS;
+        const int nrows = min(ROWS, max(0, (n - base - w + kWaves - 1) / kWaves));
+        int cnt = (j - base - w + kWaves - 1) / kWaves;
+        cnt = cnt < 0 ? 0 : (cnt > nrows ? nrows : cnt);
+        const R* kr = K + P.koff + (int64_t)j * P.npad + kperm(base + w);
+        R acc = R(0);
+        for (int m = 0; m < cnt; ++m) acc = fma(kr[m], R(1), acc);
+        ks[P.ksoff + e] = acc;
     }
 }
 
@@ -307,12 +344,10 @@ template <typename R>
 struct PairCfg;
 template <>
 struct PairCfg<float> {
-    static constexpr int kRows = 32;  // rows per wave per pass
     static constexpr int kChunkCols = kChunk;
 };
 template <>
 struct PairCfg<double> {
-    static constexpr int kRows = 16;
     static constexpr int kChunkCols = kChunk / 2;
 };
 
@@ -331,19 +366,22 @@ __device__ __forceinline__ void pair_term(R hc, R hs, R ux, R uy, R moff, R k, R
     Jj = fma(k, g, Jj);
 }
 
-// One work item = (curve, kLanes frequency slots).  Accumulators per lane (one frequency):
-//   SJ  = sum_{i<j} K(i,j) g_ij          ST  = sum_{i<j} g_ij
-//   SCa = sum_{i<j} r_i g_ij             SCb = sum_{i<j} r_j g_ij
-// with g_ij = exp(-2 sin^2(pi f (t_i - t_j)) / sigma_t^2).  Short runs are summed in R and folded
-// into FP64 once per column (over rows) or once per chunk (per row).
+// One work item = (curve, kLanes frequency slots).  Accumulators per lane (one frequency), all of
+// deviations from g = 1 so that they vanish exactly where every kernel value is 1:
+//   SJ  = sum_{i<j} K(i,j) (g_ij - 1)    ST  = sum_{i<j} (g_ij - 1)
+//   SCa = sum_{i<j} r_i (g_ij - 1)       SCb = sum_{i<j} r_j (g_ij - 1)
+// with g_ij = exp(-2 sin^2(pi f (t_i - t_j)) / sigma_t^2); the constant parts (sum K, N(N-1)/2,
+// (N-1) sum r) come from the Gram stage in FP64.  Column sums over the wave's rows are taken in R
+// and folded into FP64 per column; row sums over a chunk of columns are folded per chunk.
 template <typename R>
 __global__ void __launch_bounds__(kThreads)
 pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ order,
              FreqPlan fp, const double* __restrict__ t_all, const R* __restrict__ K_all,
-             const R* __restrict__ r_all, const R* __restrict__ rp_all, PairOut out) {
+             const R* __restrict__ r_all, const R* __restrict__ rp_all,
+             const R* __restrict__ ks_all, PairOut out) {
     using W = Warp<R>;
     using V = typename W::V;
-    constexpr int ROWS = PairCfg<R>::kRows;
+    constexpr int ROWS = rows_per_wave<R>();
     constexpr int PASS = kWaves * ROWS;
     constexpr int CH = PairCfg<R>::kChunkCols;
     constexpr int GRP = 4;  // rows skipped together in the diagonal region
@@ -398,6 +436,7 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
         const int64_t kofs = kperm(base + w);
         const R* Kbase = K_all + P.koff + kofs;
         const R* rpb = rp_all + P.poff + kofs;
+        const R* ksb = ks_all + P.ksoff + (int64_t)((base / PASS) * kWaves + w) * n;
         const int nch = (n - base + CH - 1) / CH;
 
         auto stage = [&](int j0, int buf) {
@@ -413,7 +452,6 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
             if (k + 1 < nch) stage(j0 + CH, (k + 1) & 1);
             const int buf = k & 1;
             const int jend = min(CH, n - j0);
-            R Tc = R(0), Jc = R(0), Cc = R(0);
             // Columns of this chunk.  Past the diagonal block of the pass every row of a full wave
             // pairs with every column (straight-line body); in the diagonal block, or for a wave
             // with fewer than ROWS rows, rows with i >= j are masked.
@@ -426,13 +464,16 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
                     R kk[ROWS];
 #pragma unroll
                     for (int m = 0; m < ROWS; ++m) kk[m] = kr[m];
+                    const R ksj = ksb[j];
+                    const R rj = rr[j];
                     R Tj = R(0), Jj = R(0);
 #pragma unroll
                     for (int m = 0; m < ROWS; ++m)
                         pair_term<R>(ci[m], si[m], u.x, u.y, zero, kk[m], Tj, G[m], Jj);
-                    Tc += Tj;
-                    Jc += Jj;
-                    Cc = fma(rr[j], Tj, Cc);
+                    const R dT = Tj - (R)ROWS;
+                    ST += (double)dT;
+                    SJ += (double)(Jj - ksj);
+                    SCb += (double)(rj * dT);
                 }
             } else {
                 for (int q = 0; q < jend; ++q) {
@@ -458,21 +499,22 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
                             }
                         }
                     }
-                    Tc += Tj;
-                    Jc += Jj;
-                    Cc = fma(rr[j], Tj, Cc);
+                    const R dT = Tj - (R)cnt;
+                    ST += (double)dT;
+                    SJ += (double)(Jj - ksb[j]);
+                    SCb += (double)(rr[j] * dT);
                 }
             }
-            ST += (double)Tc;
-            SJ += (double)Jc;
-            SCb += (double)Cc;
+            // Row sums of this chunk minus their number of valid pairs, weighted by r_i.
             R rk[ROWS];
 #pragma unroll
             for (int m = 0; m < ROWS; ++m) rk[m] = rpb[m];
             R Ca = R(0);
 #pragma unroll
             for (int m = 0; m < ROWS; ++m) {
-                Ca = fma(rk[m], G[m], Ca);
+                const int i = base + w + kWaves * m;
+                const int nv = (m < nrows) ? max(0, j0 + jend - max(j0, i + 1)) : 0;
+                Ca = fma(rk[m], G[m] - (R)nv, Ca);
                 G[m] = R(0);
             }
             SCa += (double)Ca;
@@ -496,9 +538,10 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
         SCb += red[(v * kLanes + lane) * 4 + 3];
     }
     const double N = (double)n;
-    const double VJ = P.A * (N * P.B + 2.0 * SJ) / (N * N);
-    const double IPt = P.A * (N + 2.0 * ST) / (N * N);
-    const double VC = P.A * (P.rsum + SCa + SCb) / (N * N * N);
+    const double npairs = 0.5 * N * (N - 1.0);
+    const double VJ = P.A * (N * P.bk + 2.0 * (P.sjc + SJ)) / (N * N);
+    const double IPt = P.A * (N + 2.0 * (npairs + ST)) / (N * N);
+    const double VC = P.A * (P.rsum + P.scc + SCa + SCb) / (N * N * N);
     const double VM = P.ipy * IPt;
     const double q = log(VJ) + log(VM) - 2.0 * log(VC);
     const double nckp = sqrt(N * P.sigma_t) / P.ipy * (VJ - VM);
@@ -735,21 +778,32 @@ template hipError_t launch_gram_finalize<double>(hipStream_t, CurveParams*, int,
                                                  double*);
 
 template <typename R>
+hipError_t launch_ksum(hipStream_t st, const CurveParams* cp, int n_curves, const R* K, R* ks) {
+    if (n_curves <= 0) return hipSuccess;
+    ksum_kernel<R><<<n_curves, kKsBlock, 0, st>>>(cp, K, ks);
+    return hipGetLastError();
+}
+template hipError_t launch_ksum<float>(hipStream_t, const CurveParams*, int, const float*, float*);
+template hipError_t launch_ksum<double>(hipStream_t, const CurveParams*, int, const double*,
+                                        double*);
+
+template <typename R>
 hipError_t launch_pairs(hipStream_t st, const CurveParams* cp, const int32_t* order,
                         int n_work_curves, const FreqPlan& fp, const double* t, const R* K,
-                        const R* r, const R* rp, const PairOut& out) {
+                        const R* r, const R* rp, const R* ks, const PairOut& out) {
     if (n_work_curves <= 0 || fp.count <= 0) return hipSuccess;
     const int tiles = (fp.count + kLanes - 1) / kLanes;
     const int64_t grid = (int64_t)tiles * n_work_curves;
-    pairs_kernel<R><<<(unsigned)grid, kThreads, 0, st>>>(cp, order, fp, t, K, r, rp, out);
+    pairs_kernel<R><<<(unsigned)grid, kThreads, 0, st>>>(cp, order, fp, t, K, r, rp, ks, out);
     return hipGetLastError();
 }
 template hipError_t launch_pairs<float>(hipStream_t, const CurveParams*, const int32_t*, int,
                                         const FreqPlan&, const double*, const float*,
-                                        const float*, const float*, const PairOut&);
+                                        const float*, const float*, const float*, const PairOut&);
 template hipError_t launch_pairs<double>(hipStream_t, const CurveParams*, const int32_t*, int,
                                          const FreqPlan&, const double*, const double*,
-                                         const double*, const double*, const PairOut&);
+                                         const double*, const double*, const double*,
+                                         const PairOut&);
 
 hipError_t launch_peaks(hipStream_t st, const CurveParams* cp, int n_curves, const double* coarse,
                         int n_coarse, double f0, double df, int top_k, int n_fine,

@@ -38,7 +38,9 @@ MAX_TOPK = 32
 
 SYMBOLS = ("qmi_create", "qmi_destroy", "qmi_last_error", "qmi_set_option", "qmi_get_stats",
            "qmi_periodogram", "qmi_best_period", "qmi_periodogram_dev", "qmi_best_period_dev",
-           "qmi_discriminate", "qmi_serve_start", "qmi_submit", "qmi_poll", "qmi_serve_stop")
+           "qmi_discriminate", "qmi_calibrate", "qmi_serve_start", "qmi_submit", "qmi_poll",
+           "qmi_serve_stop")
+SNR_EDGES = (0.0, 1.5, 2.0, 2.5, 3.5, 5.0, 10.0, 20.0, math.inf)
 
 
 class QMIError(RuntimeError):
@@ -118,6 +120,8 @@ def lib() -> ctypes.CDLL:
             f.restype = ctypes.c_int
         L.qmi_discriminate.argtypes = [V, I32, V, P(Thresholds), V]
         L.qmi_discriminate.restype = ctypes.c_int
+        L.qmi_calibrate.argtypes = [V, V, V, I32, V, I32, I32, V, V, V, V]
+        L.qmi_calibrate.restype = ctypes.c_int
         L.qmi_serve_start.argtypes = [V, P(KernelParams), P(Search), ctypes.c_size_t, I32, I32]
         L.qmi_submit.argtypes = [V, V, V, V, I32, ctypes.c_uint64]
         L.qmi_poll.argtypes = [V, V, V, I32, I32]
@@ -164,6 +168,22 @@ def discriminate(results: np.ndarray, edges: Sequence[float], th: Sequence[float
                                 out.ctypes.data)
     if rc != OK:
         raise QMIError(rc, "bad threshold table")
+    return out
+
+
+def calibrate(scores, psnr, truth, edges: Sequence[float] = SNR_EDGES, n_points: int = 5000):
+    """Per-bin F1-maximising thresholds (host-only): dict of th, f1, precision, recall."""
+    sc = _f64(scores)
+    ps = _f64(psnr)
+    tr = np.ascontiguousarray(truth, dtype=np.uint8)
+    e = _f64(edges)
+    nb = len(e) - 1
+    out = {k: np.zeros(nb) for k in ("th", "f1", "precision", "recall")}
+    rc = lib().qmi_calibrate(sc.ctypes.data, ps.ctypes.data, tr.ctypes.data, len(sc), e.ctypes.data,
+                             nb, int(n_points), out["th"].ctypes.data, out["f1"].ctypes.data,
+                             out["precision"].ctypes.data, out["recall"].ctypes.data)
+    if rc != OK:
+        raise QMIError(rc, "bad calibration arguments")
     return out
 
 
@@ -278,7 +298,8 @@ class Context:
         return res
 
     # ------------------------------------------------------------------- serving
-    def serve_start(self, sigma_t: float, f_min: float, f_max: float, n_coarse: int,
+    def serve_start(self, sigma_t: float, f_min: float = 1e-3, f_max: float = 10.0,
+                    n_coarse: int = 20000,
                     top_k: int = 10, n_fine: int = 1000, sigma_y: float = SIGMA_SILVERMAN,
                     score: int = SCORE_QMI, admit_budget_bytes: int = 0, max_batch: int = 256,
                     max_inflight: int = 2):

@@ -96,3 +96,22 @@ def test_create_without_device_fails_cleanly():
     with pytest.raises(qmi.QMIError) as ei:
         qmi.Context(0)
     assert ei.value.code == qmi.EDEVICE
+
+
+def test_calibration_matches_oracle():
+    rng = np.random.default_rng(7)
+    n = 400
+    truth = rng.random(n) < 0.5
+    psnr = rng.uniform(0.2, 30, n)
+    scores = np.where(truth, rng.normal(0.9, 0.35, n), rng.normal(0.35, 0.2, n))
+    scores[::53] = np.nan
+    for pts in (1, 2, 257, 5000):
+        got = qmi.calibrate(scores, psnr, truth, n_points=pts)
+        ref = O.calibrate_thresholds(list(scores), list(psnr), list(truth), n_points=pts)
+        assert np.array_equal(got["th"], np.array(ref["th"])), pts
+        assert np.array_equal(got["f1"], np.array(ref["f1"]))
+        assert np.array_equal(got["precision"], np.array(ref["precision"]))
+        assert np.array_equal(got["recall"], np.array(ref["recall"]))
+    # empty bins and bins without periodic members
+    got = qmi.calibrate([0.5, 0.7], [1.0, 1.2], [0, 0])
+    assert got["th"][0] == 0.7 and got["f1"][0] == 0.0 and np.isinf(got["th"][1])

@@ -291,3 +291,60 @@ def test_device_pointer_variants(ctx):
     assert np.array_equal(cd.cpu().numpy(), coarse_h)
     st = ctx.stats()
     assert st["pair_launches"] == 2 and st["pair_kernel_ms"] > 0 and st["pair_items"] > 0
+
+
+def test_graph_replay_matches_eager(ctx):
+    """The device section captured once and replayed on new data of the same shape gives the eager
+    results bit for bit, with eager work on another context between the replays."""
+    ns = [120, 333, 257]
+    A = pack([synth.survey_batch_curve(k, n=n) for k, n in enumerate(ns)])
+    B = pack([synth.survey_batch_curve(k + 50, n=n) for k, n in enumerate(ns)])
+    with qmi.Context(0) as eager:
+        eager.set_option(qmi.OPT_USE_GRAPH, 0)
+        ref = {}
+        for name, b in (("A", A), ("B", B)):
+            ref[name] = eager.best_period(b.offsets, b.t, b.y, b.e, 0.3, want_coarse=True, **SEARCH)
+            assert eager.stats()["used_graph"] == 0
+    other = synth.survey_batch_curve(99, n=64)
+    with qmi.Context(0) as g:
+        for name in ("A", "B", "A", "B", "A"):
+            b = A if name == "A" else B
+            res, coarse = g.best_period(b.offsets, b.t, b.y, b.e, 0.3, want_coarse=True, **SEARCH)
+            assert g.stats()["used_graph"] == 1
+            assert np.array_equal(res, ref[name][0])
+            assert np.array_equal(coarse, ref[name][1])
+            ctx.periodogram([0, other.n], other.t, other.y, other.e, [0.1, 0.2], 0.3)
+
+
+def test_serving_results_equal_alone(ctx):
+    """Continuous batching: requests submitted while others run are admitted into overlapping
+    launches; every result equals the same curve searched alone."""
+    import time
+
+    curves = [synth.serving_curve(k) for k in range(40)]
+    kw = dict(f_min=1e-3, f_max=10.0, n_coarse=600, top_k=4, n_fine=64)
+    alone = []
+    for c in curves[:6]:
+        r, _ = ctx.best_period([0, c.n], c.t, c.y, c.e, 0.3, **kw)
+        alone.append(r[0])
+    batch = pack(curves)
+    mixed, _ = ctx.best_period(batch.offsets, batch.t, batch.y, batch.e, 0.3, **kw)
+    for k in range(6):
+        assert np.array_equal(mixed[k], alone[k])
+    with qmi.Context(0) as srv:
+        srv.serve_start(0.3, max_batch=8, max_inflight=3, **kw)
+        got = {}
+        for k, c in enumerate(curves):
+            while not srv.submit(c.t, c.y, c.e, tag=k):
+                res, tags = srv.poll(64, 1000)
+                got.update({int(t): r for t, r in zip(tags, res)})
+            if k % 7 == 0:
+                time.sleep(0.002)
+        t0 = time.time()
+        while len(got) < len(curves) and time.time() - t0 < 60:
+            res, tags = srv.poll(64, 10000)
+            got.update({int(t): r for t, r in zip(tags, res)})
+        srv.serve_stop()
+    assert len(got) == len(curves)
+    for k in range(len(curves)):
+        assert np.array_equal(got[k], mixed[k]), k
