@@ -133,6 +133,10 @@ def main():
     E = torch.from_numpy(batch.e).to(dev)
     stream = torch.cuda.current_stream()
     ctx = qmi.Context(0, stream=stream.cuda_stream)
+    # The timed steps run the device section eagerly so that HIP events around each pair-kernel
+    # launch give its duration (at seconds per step, graph replay would change nothing measurable);
+    # graph replay is measured separately below and used by the serving loop.
+    ctx.set_option(qmi.OPT_USE_GRAPH, 0)
     kw = dict(f_min=wl["f_min"], f_max=wl["f_max"], n_coarse=wl["n_coarse"], top_k=wl["top_k"],
               n_fine=wl["n_fine"])
     st_ = wl["sigma_t"]
@@ -156,6 +160,17 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ok = int(np.sum(res["status"] == 0))
+    variant = s["pair_variant"]
+    # The same step replayed from a captured hipGraph (first call captures, second replays).
+    ctx.set_option(qmi.OPT_USE_GRAPH, 1)
+    step()
+    torch.cuda.synchronize()
+    g0 = time.perf_counter()
+    res_g = step()
+    torch.cuda.synchronize()
+    graph_ms = 1e3 * (time.perf_counter() - g0)
+    graph_used = ctx.stats()["used_graph"]
+    graph_same = bool(np.array_equal(res_g, res))
     value = nc * a.steps / dt
     ms_per_step = 1e3 * dt / a.steps
     achieved = items / (pair_ms * 1e-3) if pair_ms > 0 else float("nan")
@@ -225,11 +240,12 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e9, "peak": PEAK_ITEMS_PER_S / 1e9,
                      "unit": "G pair*freq items/s", "frac": achieved / PEAK_ITEMS_PER_S,
                      "traffic": None,
-                     "kernel": "pairs_kernel<float>", "launches": launches,
+                     "kernel": "pairs_kernel<float>", "variant": variant, "launches": launches,
                      "avg_launch_ms": pair_ms / max(launches, 1),
                      "probe_pair_items_per_s": probe and probe.get("pair_items_per_s"),
                      "probe_exp_per_s": probe and probe.get("exp_per_s"),
                      "probe_fma_per_s": probe and probe.get("fma_per_s")},
+        "graph": {"ms_per_step": graph_ms, "used": graph_used, "same_results": graph_same},
         "plain": plain,
         "serving": serve,
         "p99_ms": serve and serve["p99_ms"],

@@ -151,6 +151,8 @@ typedef struct {
     double pair_items;       /* sum over curves of N(N-1)/2 x evaluated frequencies */
     int32_t pair_launches;   /* number of pair-sum kernel launches */
     int32_t used_graph;      /* 1 if the device section ran as a captured hipGraph */
+    int32_t pair_variant;    /* pair-kernel variant used (autotuned unless QMI_OPT_TILE is set) */
+    int32_t reserved;
 } qmi_stats;
 
 /*
@@ -170,7 +172,7 @@ const char *qmi_last_error(const qmi_ctx *ctx);
 
 /* Options (qmi_set_option). */
 #define QMI_OPT_USE_GRAPH 1 /* 1: capture the device section into a hipGraph and replay it (default 1) */
-#define QMI_OPT_TILE 2      /* pair-kernel variant: 0 auto (autotuned), else a variant id */
+#define QMI_OPT_TILE 2      /* pair-kernel variant: 0 autotuned per length bucket, k > 0 variant k-1 */
 #define QMI_OPT_SYNC 3      /* reserved */
 int qmi_set_option(qmi_ctx *ctx, int32_t option, int64_t value);
 

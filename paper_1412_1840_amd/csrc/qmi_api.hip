@@ -54,15 +54,15 @@ struct qmi_ctx {
     // Device buffers, grown on demand.
     enum {
         kT, kY, kE, kCP, kOrder, kRowStart, kK, kR, kRP, kRD, kKS, kCoarse, kCoarse2, kFine, kFine2,
-        kIps, kPeakK, kNpk, kWin, kArgmax, kRes, kFreqs, kStatusDummy, kNumBufs
+        kIps, kPeakK, kNpk, kWin, kArgmax, kRes, kFreqs, kProbe, kNumBufs
     };
     Buf bufs[kNumBufs];
     // Graph cache (device section of one planned group).
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     std::vector<uint64_t> graph_key;
-    int graph_ev_used = 0;
-    std::vector<int32_t> graph_pair_ev;
+    // Autotuner: pair-kernel variant per length bucket (-1: not tuned yet).
+    int tuned[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
     // Serving.
     struct Serve;
     std::unique_ptr<Serve> serve;
@@ -197,7 +197,7 @@ size_t curve_bytes(int64_t n, int64_t F1, int64_t F2, bool fp64, bool ips, bool 
     size_t b = 0;
     b += (size_t)n * 3 * 8;                      // t, y, e
     b += (size_t)n * (size_t)npad * rs;          // K
-    b += (size_t)n * rs + (size_t)npad * rs;     // r, rp
+    b += (size_t)npad * 8;                       // rp (FP64)
     b += (size_t)n * 8;                          // rd
     b += (size_t)((n + 8 * (fp64 ? 16 : 32) - 1) / (8 * (fp64 ? 16 : 32))) * 8 * n * rs;  // ks
     b += sizeof(CurveParams) + 64;
@@ -339,8 +339,7 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
     ENSURE(qmi_ctx::kOrder, nc * sizeof(int32_t));
     ENSURE(qmi_ctx::kRowStart, nc * sizeof(int64_t));
     ENSURE(qmi_ctx::kK, std::max<int64_t>(koff, 1) * sizeof(R));
-    ENSURE(qmi_ctx::kR, std::max<int64_t>(ns, 1) * sizeof(R));
-    ENSURE(qmi_ctx::kRP, std::max<int64_t>(poff, 1) * sizeof(R));
+    ENSURE(qmi_ctx::kRP, std::max<int64_t>(poff, 1) * 8);
     ENSURE(qmi_ctx::kRD, std::max<int64_t>(ns, 1) * 8);
     ENSURE(qmi_ctx::kKS, std::max<int64_t>(ksoff, 1) * sizeof(R));
     if (!(cs.periodogram && cs.dev_outputs)) ENSURE(qmi_ctx::kCoarse, nc * F1 * 8);
@@ -388,8 +387,7 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
     }
 
     R* K = dptr<R>(ctx, qmi_ctx::kK);
-    R* r = dptr<R>(ctx, qmi_ctx::kR);
-    R* rp = dptr<R>(ctx, qmi_ctx::kRP);
+    double* rp = dptr<double>(ctx, qmi_ctx::kRP);
     double* rd = dptr<double>(ctx, qmi_ctx::kRD);
     R* ks = dptr<R>(ctx, qmi_ctx::kKS);
 
@@ -442,34 +440,59 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
     }
     DevResult* dres = cs.periodogram ? nullptr : dptr<DevResult>(ctx, qmi_ctx::kRes);
 
+    // Pair-kernel variant: forced by QMI_OPT_TILE, else the autotuned choice for this length
+    // bucket (variant 0 until the bucket has been tuned; see the end of this function).
+    std::vector<int32_t> lens;
+    for (int32_t i = 0; i < nc; ++i)
+        if (cp[i].status == QMI_OK) lens.push_back(cp[i].n);
+    int bucket = 0;
+    if (!lens.empty()) {
+        std::nth_element(lens.begin(), lens.begin() + lens.size() / 2, lens.end());
+        const int med = lens[lens.size() / 2];
+        while (bucket < 7 && (192 << bucket) <= med) ++bucket;
+    }
+    const int nvar = pair_variants<R>();
+    int variant = 0;
+    if (ctx->tile > 0) variant = (int)std::min<int64_t>(ctx->tile - 1, nvar - 1);
+    else if (!fp64 && ctx->tuned[bucket] >= 0) variant = ctx->tuned[bucket];
+    double group_items = 0.0;
+    for (int32_t i = 0; i < nc; ++i)
+        if (cp[i].status == QMI_OK) group_items += 0.5 * cp[i].n * (cp[i].n - 1.0) * (double)F1;
+    const bool tune_now = !fp64 && ctx->tile == 0 && ctx->tuned[bucket] < 0 && nvar > 1 &&
+                          group_items > 2e9;
+    ctx->stats.pair_variant = variant;
+
     // The device section: every kernel of the call, and the timing events around the pair kernels.
     // It contains no copies or allocations, so it can be captured into a hipGraph and replayed.
-    auto section = [&]() -> int {
-        record(ctx);  // device section start
+    auto section = [&](bool events) -> int {
+        auto rec = [&]() {
+            if (events) record(ctx);
+        };
+        rec();  // device section start
         HIP_OK(ctx, launch_prologue(st, dcp, nc, max_n, t, y, e));
-        HIP_OK(ctx, launch_gram<R>(st, dcp, nc, rows, drow, y, K, r, rp, rd));
+        HIP_OK(ctx, launch_gram<R>(st, dcp, nc, rows, drow, y, K, rp, rd));
         HIP_OK(ctx, launch_gram_finalize<R>(st, dcp, nc, rd, rp));
         HIP_OK(ctx, launch_ksum<R>(st, dcp, nc, K, ks));
-        pair_event_idx.push_back(ctx->ev_used);
-        record(ctx);
-        HIP_OK(ctx, launch_pairs<R>(st, dcp, dorder, nc, fp, t, K, r, rp, ks, po));
-        record(ctx);
+        if (events) pair_event_idx.push_back(ctx->ev_used);
+        rec();
+        HIP_OK(ctx, launch_pairs<R>(st, dcp, dorder, nc, fp, t, K, rd, rp, ks, po, variant));
+        rec();
         if (!cs.periodogram) {
             const qmi_search* s = cs.search;
             HIP_OK(ctx, launch_peaks(st, dcp, nc, coarse, s->n_coarse, fp.f0, fp.df, top_k,
                                      std::max(n_fine, 2), pk));
             if (refine) {
                 PairOut fo{fine, fine2, nullptr, score_kind, 0};
-                pair_event_idx.push_back(ctx->ev_used);
-                record(ctx);
-                HIP_OK(ctx, launch_pairs<R>(st, dcp, dorder, nc, ff, t, K, r, rp, ks, fo));
-                record(ctx);
+                if (events) pair_event_idx.push_back(ctx->ev_used);
+                rec();
+                HIP_OK(ctx, launch_pairs<R>(st, dcp, dorder, nc, ff, t, K, rd, rp, ks, fo, variant));
+                rec();
             }
             HIP_OK(ctx, launch_best(st, dcp, nc, coarse, coarse2, s->n_coarse, fine, fine2,
                                     refine ? top_k : 0, refine ? n_fine : 0, score_kind, fp.f0,
                                     fp.df, pk, dres));
         }
-        record(ctx);  // device section end
+        rec();  // device section end
         return QMI_OK;
     };
 
@@ -481,14 +504,15 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
         std::vector<uint64_t> key = {
             (uint64_t)fp64, (uint64_t)cs.periodogram, (uint64_t)nc, (uint64_t)rows,
             (uint64_t)max_n, (uint64_t)F1, (uint64_t)F2, (uint64_t)top_k, (uint64_t)n_fine,
-            (uint64_t)score_kind, dbits(fp.f0), dbits(fp.df), u(st), u(t), u(y), u(e), u(dcp),
-            u(dorder), u(drow), u(K), u(r), u(rp), u(rd), u(ks), u(dfreqs), u(coarse), u(coarse2),
+            (uint64_t)score_kind, (uint64_t)variant, dbits(fp.f0), dbits(fp.df), u(st), u(t), u(y),
+            u(e), u(dcp),
+            u(dorder), u(drow), u(K), u(rp), u(rd), u(ks), u(dfreqs), u(coarse), u(coarse2),
             u(po.ips), u(fine), u(fine2), u(pk.peak_k), u(pk.npk), u(pk.win), u(pk.argmax),
             u(dres)};
         if (ctx->graph_exec && key == ctx->graph_key) {
+            record(ctx);
             HIP_OK(ctx, hipGraphLaunch(ctx->graph_exec, st));
-            ctx->ev_used = ctx->graph_ev_used;
-            pair_event_idx = ctx->graph_pair_ev;
+            record(ctx);
             ran = true;
             ctx->stats.used_graph = 1;
         } else {
@@ -497,17 +521,12 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
             ctx->graph_exec = nullptr;
             ctx->graph = nullptr;
             ctx->graph_key.clear();
-            // Event objects must exist before capture starts (creation is not a stream operation,
-            // but keep the captured section free of anything but launches and records).
-            while ((int)ctx->ev.size() < 8) {
-                hipEvent_t ev;
-                HIP_OK(ctx, hipEventCreate(&ev));
-                ctx->ev.push_back(ev);
-            }
+            // The captured section holds kernel launches only (no events, copies or allocations).
             bool ok = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            int rc_sec = QMI_OK;
+            hipGraph_t graph = nullptr;
             if (ok) {
-                const int rc_sec = section();
-                hipGraph_t graph = nullptr;
+                rc_sec = section(false);
                 const bool ended = hipStreamEndCapture(st, &graph) == hipSuccess;
                 hipGraphExec_t exec = nullptr;
                 ok = rc_sec == QMI_OK && ended && graph &&
@@ -516,27 +535,30 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
                     ctx->graph = graph;
                     ctx->graph_exec = exec;
                     ctx->graph_key = key;
-                    ctx->graph_ev_used = ctx->ev_used;
-                    ctx->graph_pair_ev = pair_event_idx;
+                    record(ctx);
                     HIP_OK(ctx, hipGraphLaunch(exec, st));
+                    record(ctx);
                     ran = true;
                     ctx->stats.used_graph = 1;
-                } else {
-                    if (graph) (void)hipGraphDestroy(graph);
-                    (void)hipGetLastError();
-                    ctx->use_graph = false;  // this runtime cannot capture the section: run eagerly
-                    ctx->ev_used = 0;
-                    pair_event_idx.clear();
-                    ctx->err.clear();
                 }
-            } else {
+            }
+            if (!ok) {
+                // Capture is not available for this section: run eagerly from now on.  A stream
+                // left in a failed capture is replaced when the context owns it.
+                if (graph) (void)hipGraphDestroy(graph);
                 (void)hipGetLastError();
                 ctx->use_graph = false;
+                ctx->err.clear();
+                if (ctx->own_stream) {
+                    (void)hipStreamDestroy(ctx->stream);
+                    HIP_OK(ctx, hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+                    st = ctx->stream;
+                }
             }
         }
     }
     if (!ran) {
-        const int rc_sec = section();
+        const int rc_sec = section(true);
         if (rc_sec != QMI_OK) return rc_sec;
     }
 
@@ -607,6 +629,40 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
             if (cp[i].status == QMI_OK)
                 ctx->stats.pair_items += (double)n * (double)(n - 1) / 2.0 * (double)F1;
         }
+    }
+    if (tune_now) {
+        // Time every variant on the largest curves of this group (the first in LPT order) over a
+        // slice of the same frequency plan, into a scratch output, and keep the fastest.
+        const int pc = std::min(nc, 48);
+        FreqPlan probe = fp;
+        probe.count = (int32_t)std::min<int64_t>(F1, 64 * 24);
+        // The kernel writes slot s of curve c (a curve id, not its rank in the work order) at
+        // c * count + s, so the scratch output must cover every curve id of the group.
+        int rc2 = ensure(ctx, qmi_ctx::kProbe, (size_t)nc * probe.count * 8);
+        if (rc2 != QMI_OK) return rc2;
+        PairOut pout{dptr<double>(ctx, qmi_ctx::kProbe), nullptr, nullptr, score_kind, 0};
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        HIP_OK(ctx, hipEventCreate(&e0));
+        HIP_OK(ctx, hipEventCreate(&e1));
+        float best_ms = 0.f;
+        int best_v = 0;
+        for (int v = 0; v < nvar; ++v) {
+            HIP_OK(ctx, launch_pairs<R>(st, dcp, dorder, pc, probe, t, K, rd, rp, ks, pout, v));
+            HIP_OK(ctx, hipEventRecord(e0, st));
+            for (int rep = 0; rep < 2; ++rep)
+                HIP_OK(ctx, launch_pairs<R>(st, dcp, dorder, pc, probe, t, K, rd, rp, ks, pout, v));
+            HIP_OK(ctx, hipEventRecord(e1, st));
+            HIP_OK(ctx, hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_OK(ctx, hipEventElapsedTime(&ms, e0, e1));
+            if (v == 0 || ms < best_ms) {
+                best_ms = ms;
+                best_v = v;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        ctx->tuned[bucket] = best_v;
     }
     (void)fp64;
     return QMI_OK;

@@ -35,7 +35,7 @@ __host__ __device__ inline int64_t kperm_inv(int64_t s) {
 struct CurveParams {
     int64_t off;   // first sample in the packed t / y / e arrays
     int64_t koff;  // first element of this curve's K table
-    int64_t poff;  // first element of this curve's permuted row-sum array (npad entries)
+    int64_t poff;  // first element of this curve's permuted FP64 row-sum array (npad entries)
     int64_t ksoff; // first element of this curve's column K-sum table (passes * kWaves * n)
     int32_t n;     // samples
     int32_t npad;  // K-table row length (multiple of kPass)
@@ -50,7 +50,6 @@ struct CurveParams {
     double psnr;
     double bk;     // diagonal value of the stored K table (B rounded to the kernel type)
     double sjc;    // sum_{i<j} K(i,j)            (FP64, from the stored K table)
-    double scc;    // sum_{i<j} (r_i + r_j) = (N-1) sum_i r_i
 };
 
 // Rows per wave of the pair kernel for each arithmetic type (a pass is kWaves times this).
@@ -97,17 +96,21 @@ hipError_t launch_prologue(hipStream_t st, CurveParams* cp, int n_curves, int ma
                            const double* t, const double* y, const double* e);
 template <typename R>
 hipError_t launch_gram(hipStream_t st, CurveParams* cp, int n_curves, int64_t total_rows,
-                       const int64_t* row_curve_start, const double* y, R* K, R* r, R* rp,
+                       const int64_t* row_curve_start, const double* y, R* K, double* rp,
                        double* rd);
 template <typename R>
 hipError_t launch_gram_finalize(hipStream_t st, CurveParams* cp, int n_curves, const double* rd,
-                                R* rp);
+                                double* rp);
 template <typename R>
 hipError_t launch_ksum(hipStream_t st, const CurveParams* cp, int n_curves, const R* K, R* ks);
+// Pair-kernel variants: ids 0 .. pair_variants<R>() - 1 (0 is the default).
+template <typename R>
+int pair_variants();
 template <typename R>
 hipError_t launch_pairs(hipStream_t st, const CurveParams* cp, const int32_t* order,
                         int n_work_curves, const FreqPlan& fp, const double* t, const R* K,
-                        const R* r, const R* rp, const R* ks, const PairOut& out);
+                        const double* rd, const double* rp, const R* ks, const PairOut& out,
+                        int variant);
 hipError_t launch_peaks(hipStream_t st, const CurveParams* cp, int n_curves, const double* coarse,
                         int n_coarse, double f0, double df, int top_k, int n_fine,
                         const PeakOut& po);

@@ -172,8 +172,8 @@ constexpr int kGramBlock = 256;
 template <typename R>
 __global__ void __launch_bounds__(kGramBlock)
 gram_kernel(const CurveParams* __restrict__ cp, const int64_t* __restrict__ row_curve_start,
-            int n_curves, const double* __restrict__ y, R* __restrict__ K, R* __restrict__ r,
-            R* __restrict__ rp, double* __restrict__ rd) {
+            int n_curves, const double* __restrict__ y, R* __restrict__ K,
+            double* __restrict__ rp, double* __restrict__ rd) {
     __shared__ double red[kGramBlock / 64 + 1];
     const int64_t row = blockIdx.x;
     // Curve of this row: binary search over the prefix of row counts.
@@ -203,8 +203,7 @@ gram_kernel(const CurveParams* __restrict__ cp, const int64_t* __restrict__ row_
     }
     acc = block_sum<kGramBlock>(acc, red);
     if (threadIdx.x == 0) {
-        r[P.off + j] = (R)acc;
-        rp[P.poff + kperm(j)] = (R)acc;
+        rp[P.poff + kperm(j)] = acc;
         rd[P.off + j] = acc;
     }
 }
@@ -215,13 +214,13 @@ constexpr int kFinBlock = 256;
 template <typename R>
 __global__ void __launch_bounds__(kFinBlock)
 gram_finalize_kernel(CurveParams* __restrict__ cp, const double* __restrict__ rd,
-                     R* __restrict__ rp) {
+                     double* __restrict__ rp) {
     __shared__ double red[kFinBlock / 64 + 1];
     const int c = blockIdx.x;
     const CurveParams P = cp[c];
     if (P.status != 0 || P.npad == 0) return;
     for (int s = threadIdx.x; s < P.npad; s += kFinBlock)
-        if (kperm_inv(s) >= P.n) rp[P.poff + s] = R(0);
+        if (kperm_inv(s) >= P.n) rp[P.poff + s] = 0.0;
     double acc = 0.0;
     for (int i = threadIdx.x; i < P.n; i += kFinBlock) acc += rd[P.off + i];
     acc = block_sum<kFinBlock>(acc, red);
@@ -232,7 +231,6 @@ gram_finalize_kernel(CurveParams* __restrict__ cp, const double* __restrict__ rd
         cp[c].ipy = acc / (N * N);
         cp[c].bk = bk;
         cp[c].sjc = 0.5 * (acc - N * bk);  // the table is symmetric: sum_{i<j} K = (sum - diag)/2
-        cp[c].scc = (N - 1.0) * acc;
     }
 }
 
@@ -340,50 +338,44 @@ struct Warp<double> {
     __device__ __forceinline__ static double kexp(double a) { return exp2(a); }
 };
 
-template <typename R>
-struct PairCfg;
-template <>
-struct PairCfg<float> {
-    static constexpr int kChunkCols = kChunk;
-};
-template <>
-struct PairCfg<double> {
-    static constexpr int kChunkCols = kChunk / 2;
-};
 
 // One term of the pair sums for row i of this wave and the current column j: the kernel value
 // g = exp2(-(d^2 + moff)) with d = h_s(i) h_c(j) - h_c(i) h_s(j) and moff = 0 (or +inf for a row that
-// is masked out, giving g = 0), added to the column sum Tj, the row sum G and the K-weighted column
-// sum Jj.
+// is masked out, giving g = 0), added to a column partial T, the row sum G and a K-weighted column
+// partial J.
 template <typename R>
-__device__ __forceinline__ void pair_term(R hc, R hs, R ux, R uy, R moff, R k, R& Tj, R& G, R& Jj) {
+__device__ __forceinline__ void pair_term(R hc, R hs, R ux, R uy, R moff, R k, R& T, R& G, R& J) {
     const R pr = hc * uy;
     const R d = fma(hs, ux, -pr);
     const R a = fma(d, d, moff);
     const R g = Warp<R>::kexp(-a);
-    Tj += g;
+    T += g;
     G += g;
-    Jj = fma(k, g, Jj);
+    J = fma(k, g, J);
 }
 
-// One work item = (curve, kLanes frequency slots).  Accumulators per lane (one frequency), all of
-// deviations from g = 1 so that they vanish exactly where every kernel value is 1:
-//   SJ  = sum_{i<j} K(i,j) (g_ij - 1)    ST  = sum_{i<j} (g_ij - 1)
-//   SCa = sum_{i<j} r_i (g_ij - 1)       SCb = sum_{i<j} r_j (g_ij - 1)
-// with g_ij = exp(-2 sin^2(pi f (t_i - t_j)) / sigma_t^2); the constant parts (sum K, N(N-1)/2,
-// (N-1) sum r) come from the Gram stage in FP64.  Column sums over the wave's rows are taken in R
-// and folded into FP64 per column; row sums over a chunk of columns are folded per chunk.
-template <typename R>
-__global__ void __launch_bounds__(kThreads)
+// One work item = (curve, kLanes frequency slots).  Accumulators per lane (one frequency), FP64:
+//   ST  = sum_{i<j} g_ij                 SJ  = sum_{i<j} K(i,j) g_ij - sum_{i<j} K(i,j)
+//   SCa = sum_{i<j} r_i g_ij             SCb = sum_{i<j} r_j g_ij
+// with g_ij = exp(-2 sin^2(pi f (t_i - t_j)) / sigma_t^2) and r_i = sum_k K(i,k).  A column's terms
+// over the wave's rows are summed in R in four interleaved partials (rows m mod 4) and folded into
+// FP64 per column; the r-weighted sums multiply R sums by FP64 row sums (exact products).  Where all
+// kernel values are 1 (coincident phases, f = 0) every R sum is exact: the column sums of g and of
+// the row sums are integers, and the K-weighted column sum equals, bit for bit, the precomputed
+// sum of K over the same rows in the same order, so that SJ is 0 and the scores come out exactly.
+// Variants (chosen by the host autotuner): WPE is the occupancy target in waves per SIMD (2: the
+// registers of 2 waves, no spills; 4: at most 128 VGPRs, so two workgroups share a CU), CH the
+// columns per LDS chunk.
+template <typename R, int WPE, int CH>
+__global__ void __launch_bounds__(kThreads, WPE)
 pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ order,
              FreqPlan fp, const double* __restrict__ t_all, const R* __restrict__ K_all,
-             const R* __restrict__ r_all, const R* __restrict__ rp_all,
+             const double* __restrict__ rd_all, const double* __restrict__ rp_all,
              const R* __restrict__ ks_all, PairOut out) {
     using W = Warp<R>;
     using V = typename W::V;
     constexpr int ROWS = rows_per_wave<R>();
     constexpr int PASS = kWaves * ROWS;
-    constexpr int CH = PairCfg<R>::kChunkCols;
     constexpr int GRP = 4;  // rows skipped together in the diagonal region
     __shared__ V ph[2][CH][kLanes];
 
@@ -414,7 +406,7 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
 
     const int n = P.n;
     const double* t = t_all + P.off;
-    const R* rr = r_all + P.off;
+    const double* rr = rd_all + P.off;
     const double scale = sqrt(sqrt(2.0 * kLog2e) / P.sigma_t);
     const R zero = R(0);
     const R pinf = uniform((R)INFINITY);
@@ -435,7 +427,7 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
         }
         const int64_t kofs = kperm(base + w);
         const R* Kbase = K_all + P.koff + kofs;
-        const R* rpb = rp_all + P.poff + kofs;
+        const double* rpb = rp_all + P.poff + kofs;
         const R* ksb = ks_all + P.ksoff + (int64_t)((base / PASS) * kWaves + w) * n;
         const int nch = (n - base + CH - 1) / CH;
 
@@ -465,15 +457,17 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
 #pragma unroll
                     for (int m = 0; m < ROWS; ++m) kk[m] = kr[m];
                     const R ksj = ksb[j];
-                    const R rj = rr[j];
-                    R Tj = R(0), Jj = R(0);
+                    const double rj = rr[j];
+                    R T4[4] = {R(0), R(0), R(0), R(0)}, J4[4] = {R(0), R(0), R(0), R(0)};
 #pragma unroll
                     for (int m = 0; m < ROWS; ++m)
-                        pair_term<R>(ci[m], si[m], u.x, u.y, zero, kk[m], Tj, G[m], Jj);
-                    const R dT = Tj - (R)ROWS;
-                    ST += (double)dT;
-                    SJ += (double)(Jj - ksj);
-                    SCb += (double)(rj * dT);
+                        pair_term<R>(ci[m], si[m], u.x, u.y, zero, kk[m], T4[m & 3], G[m], J4[m & 3]);
+                    const R Tq = (T4[0] + T4[1]) + (T4[2] + T4[3]);
+                    const R Jq = (J4[0] + J4[1]) + (J4[2] + J4[3]);
+                    const double Td = (double)Tq;
+                    ST += Td;
+                    SJ += (double)(Jq - ksj);
+                    SCb = fma(Td, rj, SCb);
                 }
             } else {
                 for (int q = 0; q < jend; ++q) {
@@ -486,38 +480,38 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
                     R kk[ROWS];
 #pragma unroll
                     for (int m = 0; m < ROWS; ++m) kk[m] = kr[m];
-                    R Tj = R(0), Jj = R(0);
-                    // Masked rows get an exponent offset of +inf (g = 0); groups of GRP rows that
-                    // are entirely masked are skipped.  cnt and the branches are wave-uniform.
+                    R T4[4] = {R(0), R(0), R(0), R(0)}, J4[4] = {R(0), R(0), R(0), R(0)};
+                    // Masked rows get an exponent offset of +inf (g = 0, adding exactly nothing);
+                    // groups of GRP rows that are entirely masked are skipped.  cnt and the
+                    // branches are wave-uniform.
 #pragma unroll
                     for (int g0 = 0; g0 < ROWS; g0 += GRP) {
                         if (g0 < cnt) {
 #pragma unroll
                             for (int m = g0; m < g0 + GRP; ++m) {
                                 const R off = (m < cnt) ? zero : pinf;
-                                pair_term<R>(ci[m], si[m], u.x, u.y, off, kk[m], Tj, G[m], Jj);
+                                pair_term<R>(ci[m], si[m], u.x, u.y, off, kk[m], T4[m & 3], G[m],
+                                             J4[m & 3]);
                             }
                         }
                     }
-                    const R dT = Tj - (R)cnt;
-                    ST += (double)dT;
-                    SJ += (double)(Jj - ksb[j]);
-                    SCb += (double)(rr[j] * dT);
+                    const R Tq = (T4[0] + T4[1]) + (T4[2] + T4[3]);
+                    const R Jq = (J4[0] + J4[1]) + (J4[2] + J4[3]);
+                    const double Td = (double)Tq;
+                    ST += Td;
+                    SJ += (double)(Jq - ksb[j]);
+                    SCb = fma(Td, rr[j], SCb);
                 }
             }
-            // Row sums of this chunk minus their number of valid pairs, weighted by r_i.
-            R rk[ROWS];
+            // Row sums of this chunk, weighted by the FP64 row sums r_i.
+            double rk[ROWS];
 #pragma unroll
             for (int m = 0; m < ROWS; ++m) rk[m] = rpb[m];
-            R Ca = R(0);
 #pragma unroll
             for (int m = 0; m < ROWS; ++m) {
-                const int i = base + w + kWaves * m;
-                const int nv = (m < nrows) ? max(0, j0 + jend - max(j0, i + 1)) : 0;
-                Ca = fma(rk[m], G[m] - (R)nv, Ca);
+                SCa = fma((double)G[m], rk[m], SCa);
                 G[m] = R(0);
             }
-            SCa += (double)Ca;
             __syncthreads();
         }
     }
@@ -538,10 +532,9 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
         SCb += red[(v * kLanes + lane) * 4 + 3];
     }
     const double N = (double)n;
-    const double npairs = 0.5 * N * (N - 1.0);
     const double VJ = P.A * (N * P.bk + 2.0 * (P.sjc + SJ)) / (N * N);
-    const double IPt = P.A * (N + 2.0 * (npairs + ST)) / (N * N);
-    const double VC = P.A * (P.rsum + P.scc + SCa + SCb) / (N * N * N);
+    const double IPt = P.A * (N + 2.0 * ST) / (N * N);
+    const double VC = P.A * (P.rsum + SCa + SCb) / (N * N * N);
     const double VM = P.ipy * IPt;
     const double q = log(VJ) + log(VM) - 2.0 * log(VC);
     const double nckp = sqrt(N * P.sigma_t) / P.ipy * (VJ - VM);
@@ -753,27 +746,27 @@ hipError_t launch_prologue(hipStream_t st, CurveParams* cp, int n_curves, int ma
 
 template <typename R>
 hipError_t launch_gram(hipStream_t st, CurveParams* cp, int n_curves, int64_t total_rows,
-                       const int64_t* row_curve_start, const double* y, R* K, R* r, R* rp,
+                       const int64_t* row_curve_start, const double* y, R* K, double* rp,
                        double* rd) {
     if (total_rows <= 0) return hipSuccess;
     gram_kernel<R><<<(unsigned)total_rows, kGramBlock, 0, st>>>(cp, row_curve_start, n_curves, y,
-                                                                 K, r, rp, rd);
+                                                                 K, rp, rd);
     return hipGetLastError();
 }
 template hipError_t launch_gram<float>(hipStream_t, CurveParams*, int, int64_t, const int64_t*,
-                                       const double*, float*, float*, float*, double*);
+                                       const double*, float*, double*, double*);
 template hipError_t launch_gram<double>(hipStream_t, CurveParams*, int, int64_t, const int64_t*,
-                                        const double*, double*, double*, double*, double*);
+                                        const double*, double*, double*, double*);
 
 template <typename R>
 hipError_t launch_gram_finalize(hipStream_t st, CurveParams* cp, int n_curves, const double* rd,
-                                R* rp) {
+                                double* rp) {
     if (n_curves <= 0) return hipSuccess;
     gram_finalize_kernel<R><<<n_curves, kFinBlock, 0, st>>>(cp, rd, rp);
     return hipGetLastError();
 }
 template hipError_t launch_gram_finalize<float>(hipStream_t, CurveParams*, int, const double*,
-                                                float*);
+                                                double*);
 template hipError_t launch_gram_finalize<double>(hipStream_t, CurveParams*, int, const double*,
                                                  double*);
 
@@ -788,22 +781,49 @@ template hipError_t launch_ksum<double>(hipStream_t, const CurveParams*, int, co
                                         double*);
 
 template <typename R>
+int pair_variants() {
+    return sizeof(R) == 4 ? 4 : 1;
+}
+template int pair_variants<float>();
+template int pair_variants<double>();
+
+template <typename R, int WPE, int CH>
+static hipError_t launch_pairs_v(hipStream_t st, const CurveParams* cp, const int32_t* order,
+                                 unsigned grid, const FreqPlan& fp, const double* t, const R* K,
+                                 const double* r, const double* rp, const R* ks,
+                                 const PairOut& out) {
+    pairs_kernel<R, WPE, CH><<<grid, kThreads, 0, st>>>(cp, order, fp, t, K, r, rp, ks, out);
+    return hipGetLastError();
+}
+
+template <typename R>
 hipError_t launch_pairs(hipStream_t st, const CurveParams* cp, const int32_t* order,
                         int n_work_curves, const FreqPlan& fp, const double* t, const R* K,
-                        const R* r, const R* rp, const R* ks, const PairOut& out) {
+                        const double* r, const double* rp, const R* ks, const PairOut& out,
+                        int variant) {
     if (n_work_curves <= 0 || fp.count <= 0) return hipSuccess;
     const int tiles = (fp.count + kLanes - 1) / kLanes;
-    const int64_t grid = (int64_t)tiles * n_work_curves;
-    pairs_kernel<R><<<(unsigned)grid, kThreads, 0, st>>>(cp, order, fp, t, K, r, rp, ks, out);
-    return hipGetLastError();
+    const unsigned grid = (unsigned)((int64_t)tiles * n_work_curves);
+    if constexpr (sizeof(R) == 4) {
+        switch (variant) {
+            case 1: return launch_pairs_v<R, 4, 64>(st, cp, order, grid, fp, t, K, r, rp, ks, out);
+            case 2: return launch_pairs_v<R, 2, 32>(st, cp, order, grid, fp, t, K, r, rp, ks, out);
+            case 3: return launch_pairs_v<R, 4, 32>(st, cp, order, grid, fp, t, K, r, rp, ks, out);
+            default: return launch_pairs_v<R, 2, 64>(st, cp, order, grid, fp, t, K, r, rp, ks, out);
+        }
+    } else {
+        (void)variant;
+        return launch_pairs_v<R, 2, 32>(st, cp, order, grid, fp, t, K, r, rp, ks, out);
+    }
 }
 template hipError_t launch_pairs<float>(hipStream_t, const CurveParams*, const int32_t*, int,
                                         const FreqPlan&, const double*, const float*,
-                                        const float*, const float*, const float*, const PairOut&);
+                                        const double*, const double*, const float*,
+                                        const PairOut&, int);
 template hipError_t launch_pairs<double>(hipStream_t, const CurveParams*, const int32_t*, int,
                                          const FreqPlan&, const double*, const double*,
                                          const double*, const double*, const double*,
-                                         const PairOut&);
+                                         const PairOut&, int);
 
 hipError_t launch_peaks(hipStream_t st, const CurveParams* cp, int n_curves, const double* coarse,
                         int n_coarse, double f0, double df, int top_k, int n_fine,

@@ -73,7 +73,8 @@ class Thresholds(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("pair_kernel_ms", ctypes.c_double), ("device_ms", ctypes.c_double),
                 ("pair_items", ctypes.c_double), ("pair_launches", ctypes.c_int32),
-                ("used_graph", ctypes.c_int32)]
+                ("used_graph", ctypes.c_int32), ("pair_variant", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 RESULT_DTYPE = np.dtype([("f_best", "f8"), ("period", "f8"), ("score", "f8"), ("score_qmi", "f8"),

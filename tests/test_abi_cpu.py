@@ -47,6 +47,7 @@ def test_header_constants_match_binding():
 
 
 def test_struct_sizes():
+    assert ctypes.sizeof(qmi.Stats) == 40
     assert ctypes.sizeof(qmi.Batch) == 40
     assert ctypes.sizeof(qmi.KernelParams) == 24
     assert ctypes.sizeof(qmi.Search) == 32

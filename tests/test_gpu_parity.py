@@ -290,7 +290,14 @@ def test_device_pointer_variants(ctx):
     assert np.array_equal(res_d, res_h)
     assert np.array_equal(cd.cpu().numpy(), coarse_h)
     st = ctx.stats()
-    assert st["pair_launches"] == 2 and st["pair_kernel_ms"] > 0 and st["pair_items"] > 0
+    assert st["device_ms"] > 0 and st["pair_items"] > 0
+    if not st["used_graph"]:
+        assert st["pair_launches"] == 2 and st["pair_kernel_ms"] > 0
+    with qmi.Context(0) as eager:
+        eager.set_option(qmi.OPT_USE_GRAPH, 0)
+        eager.best_period_dev(b.offsets, T, Y, E, 0.3, coarse_out=cd, **SEARCH)
+        st = eager.stats()
+        assert st["used_graph"] == 0 and st["pair_launches"] == 2 and st["pair_kernel_ms"] > 0
 
 
 def test_graph_replay_matches_eager(ctx):
@@ -348,3 +355,41 @@ def test_serving_results_equal_alone(ctx):
     assert len(got) == len(curves)
     for k in range(len(curves)):
         assert np.array_equal(got[k], mixed[k]), k
+
+
+def test_pair_kernel_variants_agree(ctx):
+    """Every pair-kernel variant the autotuner can pick meets the oracle bar; variants that differ
+    only in occupancy give identical bits."""
+    curves = [synth.survey_batch_curve(k, n=n) for k, n in enumerate([70, 300, 777])]
+    b = pack(curves)
+    freqs = O.linear_grid(1e-3, 10.0, 190)
+    refs = [O.qmi(oracle_ips(c, freqs)) for c in curves]
+    out = {}
+    with qmi.Context(0) as c2:
+        for v in range(1, 5):
+            c2.set_option(qmi.OPT_TILE, v)
+            sc, _, _, _ = c2.periodogram(b.offsets, b.t, b.y, b.e, freqs, 0.3)
+            assert c2.stats()["pair_variant"] == v - 1
+            out[v] = sc
+            for k in range(len(curves)):
+                assert floor_rel(sc[k], refs[k]).max() <= QMI_TOL, (v, k)
+    assert np.array_equal(out[1], out[2])  # chunk 64, occupancy 2 vs 4
+    assert np.array_equal(out[3], out[4])  # chunk 32
+
+
+def test_autotune_on_batch_larger_than_probe(ctx):
+    """The autotuner probes the largest curves of a batch on a slice of the frequency plan; with
+    more curves than the probe uses, the probe's scratch output must still cover every curve id.
+    The tuned result must match a forced default variant within the parity bar."""
+    curves = [synth.survey_batch_curve(k, n=300 + (k % 7) * 13) for k in range(72)]
+    b = pack(curves)
+    kw = dict(f_min=1e-3, f_max=10.0, n_coarse=2400, top_k=2, n_fine=32)
+    with qmi.Context(0) as tuned, qmi.Context(0) as fixed:
+        fixed.set_option(qmi.OPT_TILE, 1)
+        r_t, c_t = tuned.best_period(b.offsets, b.t, b.y, b.e, 0.3, want_coarse=True, **kw)
+        r_f, c_f = fixed.best_period(b.offsets, b.t, b.y, b.e, 0.3, want_coarse=True, **kw)
+        r_t2, c_t2 = tuned.best_period(b.offsets, b.t, b.y, b.e, 0.3, want_coarse=True, **kw)
+    assert np.all(r_t["status"] == 0)
+    for k in range(len(curves)):
+        assert floor_rel(c_t[k], c_f[k]).max() <= QMI_TOL
+        assert floor_rel(c_t2[k], c_f[k]).max() <= QMI_TOL
