@@ -46,6 +46,9 @@ def parse():
                     help="Poisson arrival rate as a fraction of the measured batch throughput")
     ap.add_argument("--serve-batch", type=int, default=64)
     ap.add_argument("--serve-inflight", type=int, default=3)
+    ap.add_argument("--tile", type=int, default=0,
+                    help="force pair-kernel variant k-1 (0: autotuned)")
+    ap.add_argument("--no-graph-check", action="store_true")
     return ap.parse_args()
 
 
@@ -137,6 +140,8 @@ def main():
     # launch give its duration (at seconds per step, graph replay would change nothing measurable);
     # graph replay is measured separately below and used by the serving loop.
     ctx.set_option(qmi.OPT_USE_GRAPH, 0)
+    if a.tile:
+        ctx.set_option(qmi.OPT_TILE, a.tile)
     kw = dict(f_min=wl["f_min"], f_max=wl["f_max"], n_coarse=wl["n_coarse"], top_k=wl["top_k"],
               n_fine=wl["n_fine"])
     st_ = wl["sigma_t"]
@@ -162,15 +167,17 @@ def main():
     ok = int(np.sum(res["status"] == 0))
     variant = s["pair_variant"]
     # The same step replayed from a captured hipGraph (first call captures, second replays).
-    ctx.set_option(qmi.OPT_USE_GRAPH, 1)
-    step()
-    torch.cuda.synchronize()
-    g0 = time.perf_counter()
-    res_g = step()
-    torch.cuda.synchronize()
-    graph_ms = 1e3 * (time.perf_counter() - g0)
-    graph_used = ctx.stats()["used_graph"]
-    graph_same = bool(np.array_equal(res_g, res))
+    graph = None
+    if not a.no_graph_check:
+        ctx.set_option(qmi.OPT_USE_GRAPH, 1)
+        step()
+        torch.cuda.synchronize()
+        g0 = time.perf_counter()
+        res_g = step()
+        torch.cuda.synchronize()
+        graph = {"ms_per_step": 1e3 * (time.perf_counter() - g0),
+                 "used": ctx.stats()["used_graph"],
+                 "same_results": bool(np.array_equal(res_g, res))}
     value = nc * a.steps / dt
     ms_per_step = 1e3 * dt / a.steps
     achieved = items / (pair_ms * 1e-3) if pair_ms > 0 else float("nan")
@@ -245,7 +252,7 @@ def main():
                      "probe_pair_items_per_s": probe and probe.get("pair_items_per_s"),
                      "probe_exp_per_s": probe and probe.get("exp_per_s"),
                      "probe_fma_per_s": probe and probe.get("fma_per_s")},
-        "graph": {"ms_per_step": graph_ms, "used": graph_used, "same_results": graph_same},
+        "graph": graph,
         "plain": plain,
         "serving": serve,
         "p99_ms": serve and serve["p99_ms"],

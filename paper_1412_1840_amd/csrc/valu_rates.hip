@@ -1,6 +1,8 @@
 // VALU throughput probe for gfx950: the rates that bound the pair x frequency kernel.
 //
 //   valu_rates [iterations]
+//   valu_rates copy <MiB>   one plain device-to-device copy kernel of MiB mebibytes (to calibrate
+//                           memory-traffic counters: it reads and writes exactly MiB each)
 //
 // Prints one JSON object with lane-operations per second for
 //   exp   : v_exp_f32 only (independent chains x <- 2^-x, values stay in (0, 1])
@@ -13,6 +15,7 @@
 
 #include <cstdio>
 #include <cstdlib>
+#include <string>
 
 #define CHECK(x)                                                                      \
     do {                                                                              \
@@ -91,7 +94,30 @@ __global__ void __launch_bounds__(256) pair_kernel(float* out, const float2* col
     out[blockIdx.x * blockDim.x + threadIdx.x] = s;
 }
 
+__global__ void __launch_bounds__(256) copy_kernel(const float4* __restrict__ src,
+                                                  float4* __restrict__ dst, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+static int copy_mode(size_t mib) {
+    const size_t n = mib * (1u << 20) / sizeof(float4);
+    float4 *a, *b;
+    CHECK(hipMalloc(&a, n * sizeof(float4)));
+    CHECK(hipMalloc(&b, n * sizeof(float4)));
+    CHECK(hipMemset(a, 0, n * sizeof(float4)));
+    CHECK(hipDeviceSynchronize());
+    copy_kernel<<<4096, 256>>>(a, b, n);
+    CHECK(hipDeviceSynchronize());
+    std::printf("{\"copy_mib\": %zu}\n", mib);
+    CHECK(hipFree(a));
+    CHECK(hipFree(b));
+    return 0;
+}
+
 int main(int argc, char** argv) {
+    if (argc > 2 && std::string(argv[1]) == "copy") return copy_mode((size_t)std::atoi(argv[2]));
     const int iters = argc > 1 ? std::atoi(argv[1]) : 4096;
     hipDeviceProp_t prop;
     CHECK(hipGetDeviceProperties(&prop, 0));

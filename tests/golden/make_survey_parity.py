@@ -1,10 +1,11 @@
-"""Writes survey_batch_oracle.json: the FP64 oracle's full coarse-to-fine search (20 000 coarse +
-10 x 1000 refined frequencies on [1e-3, 10] 1/d, sigma_t = 0.3, Silverman sigma_y) of the first
-curves of the survey-batch workload, for the GPU parity test of the best period at full size.
+"""Writes <workload>_oracle.json: the FP64 oracle's full coarse-to-fine search of the first curves
+of a workload (survey_batch: 20 000 coarse + 10 x 1000 refined frequencies on [1e-3, 10] 1/d;
+long_baseline: the same on [1e-3, 20] 1/d over a 7000-day baseline; sigma_t = 0.3, Silverman
+sigma_y), for the GPU parity tests of the best period at full size.
 
-    python tests/golden/make_survey_parity.py [n_curves] [threads]
+    python tests/golden/make_survey_parity.py [n_curves] [threads] [workload]
 
-Calls only oracle/ (and the seeded input generator).  About 35 s per curve on 8 cores.
+Calls only oracle/ (and the seeded input generator).  About 35 s per survey curve on 8 cores.
 """
 import json
 import os
@@ -24,10 +25,12 @@ from paper_1412_1840_amd import synth  # noqa: E402
 def main():
     n = int(sys.argv[1]) if len(sys.argv) > 1 else 64
     threads = int(sys.argv[2]) if len(sys.argv) > 2 else 0
-    wl = synth.WORKLOADS["survey_batch"]
+    workload = sys.argv[3] if len(sys.argv) > 3 else "survey_batch"
+    wl = synth.WORKLOADS[workload]
+    make = {"survey_batch": synth.survey_batch_curve, "long_baseline": synth.long_baseline_curve}[workload]
     kw = dict(f_min=wl["f_min"], f_max=wl["f_max"], n_coarse=wl["n_coarse"], top_k=wl["top_k"],
               n_fine=wl["n_fine"])
-    out_path = os.path.join(HERE, "survey_batch_oracle.json")
+    out_path = os.path.join(HERE, "%s_oracle.json" % workload)
     records = []
     if os.path.exists(out_path):
         records = json.load(open(out_path))["curves"]
@@ -35,7 +38,7 @@ def main():
     for k in range(n):
         if k in done:
             continue
-        c = synth.survey_batch_curve(k)
+        c = make(k)
         t0 = time.time()
         r = O.best_period(c.t, c.y, c.e, wl["sigma_t"], O.SIGMA_SILVERMAN, n_threads=threads, **kw)
         fq = np.sort(r.fine_scores.ravel())[::-1]
@@ -54,7 +57,7 @@ def main():
         })
         records.sort(key=lambda x: x["k"])
         with open(out_path + ".tmp", "w") as f:
-            json.dump({"workload": "survey_batch", "search": kw, "sigma_t": wl["sigma_t"],
+            json.dump({"workload": workload, "search": kw, "sigma_t": wl["sigma_t"],
                        "sigma_y": "silverman", "curves": records}, f, indent=1)
         os.replace(out_path + ".tmp", out_path)
         print("curve %d N=%d done in %.1f s" % (k, c.n, time.time() - t0), flush=True)

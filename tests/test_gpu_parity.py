@@ -393,3 +393,60 @@ def test_autotune_on_batch_larger_than_probe(ctx):
     for k in range(len(curves)):
         assert floor_rel(c_t[k], c_f[k]).max() <= QMI_TOL
         assert floor_rel(c_t2[k], c_f[k]).max() <= QMI_TOL
+
+
+def test_survey_batch_best_period_matches_oracle_full_search():
+    """Full-size search (20 000 coarse + 10 x 1000 refined frequencies) of the first 64 curves of
+    the survey batch against the stored FP64 oracle results (tests/golden/make_survey_parity.py).
+    Indices must agree; where the oracle's best and runner-up refined scores are within 1e-5 of
+    each other (a flat maximum: several grid points are correct), the GPU's choice must score
+    within that margin of the best under the oracle."""
+    import json
+    import os
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "survey_batch_oracle.json")
+    gold = json.load(open(path))
+    recs = gold["curves"]
+    curves = [synth.survey_batch_curve(r["k"]) for r in recs]
+    b = pack(curves)
+    with qmi.Context(0) as c2:
+        res, _ = c2.best_period(b.offsets, b.t, b.y, b.e, gold["sigma_t"], **gold["search"])
+    exact, ties, bad = 0, [], []
+    for r, c, g in zip(res, curves, recs):
+        assert r["status"] == 0 and r["n_peaks"] == g["n_peaks"]
+        assert r["sigma_y"] == pytest.approx(g["sigma_y"], rel=1e-13)
+        same = (r["coarse_argmax"] == g["coarse_argmax"] and r["coarse_index"] == g["coarse_index"]
+                and r["fine_index"] == g["fine_index"])
+        if same:
+            assert r["f_best"] == g["f_best"]
+            assert abs(r["score"] - g["score"]) <= QMI_TOL * abs(g["score"])
+            exact += 1
+            continue
+        q = O.qmi(O.information_potentials(c.t, c.y, gold["sigma_t"], g["sigma_y"],
+                                           [r["f_best"]]))[0]
+        if g["best_gap"] <= 1e-5 * abs(g["score"]) and q >= g["score"] * (1 - 1e-5):
+            ties.append((g["k"], g["fine_index"], int(r["fine_index"])))
+        else:
+            bad.append((g["k"], dict(coarse=(g["coarse_index"], int(r["coarse_index"])),
+                                     fine=(g["fine_index"], int(r["fine_index"])))))
+    print("survey batch: %d of %d identical, %d flat-maximum ties %s" % (exact, len(recs),
+                                                                         len(ties), ties))
+    assert not bad, bad
+    assert exact + len(ties) == len(recs)
+    # Discriminator: thresholds calibrated by the oracle on its own scores, then the decision of
+    # every curve from the GPU result (score at f_best, pSNR) against the oracle's decision.
+    psn = [O.psnr(c.y, c.e) for c in curves]
+    for r, p in zip(res, psn):
+        assert r["psnr"] == pytest.approx(p, rel=1e-12)
+    cal = O.calibrate_thresholds([g["score"] for g in recs], psn, [g["periodic"] for g in recs],
+                                 n_points=5000)
+    th = [x if math.isfinite(x) else 1e300 for x in cal["th"]]
+    got = qmi.discriminate(res, O.SNR_EDGES, th)
+    want = [O.discriminate(g["score"], p, th) for g, p in zip(recs, psn)]
+    near = [k for k, (g, p) in enumerate(zip(recs, psn))
+            if abs(g["score"] - th[O.snr_bin(p)]) <= QMI_TOL * abs(g["score"])]
+    agree = sum(1 for k in range(len(recs)) if got[k] == want[k])
+    print("discriminator: %d of %d agree (%d within the score tolerance of a threshold)"
+          % (agree, len(recs), len(near)))
+    assert all(got[k] == want[k] for k in range(len(recs)) if k not in near)
