@@ -46,19 +46,28 @@ def parse():
                     help="Poisson arrival rate as a fraction of the measured batch throughput")
     ap.add_argument("--serve-batch", type=int, default=64)
     ap.add_argument("--serve-inflight", type=int, default=3)
+    ap.add_argument("--serve-sweep", default="",
+                    help="comma-separated loads (fractions of the saturated serving throughput, "
+                         "measured first); replaces --serve-load")
+    ap.add_argument("--serve-warmup", type=int, default=0,
+                    help="requests served first and left out of the latency statistics")
     ap.add_argument("--tile", type=int, default=0,
                     help="force pair-kernel variant k-1 (0: autotuned)")
     ap.add_argument("--no-graph-check", action="store_true")
     return ap.parse_args()
 
 
-def serving(qmi, synth, wl, st_, rate, n_req, max_batch, inflight):
+def serving(qmi, synth, wl, st_, rate, n_req, max_batch, inflight, warmup=0, curves=None):
     """Poisson stream of single-curve requests (serving-stream lengths, survey mix and search)
-    into the continuous-batching loop; latency = completion (poll) - arrival, host clock."""
+    into the continuous-batching loop; latency = completion (poll) - arrival, host clock.
+    rate = inf submits every request at once (saturated throughput).  The first ``warmup``
+    requests are served but left out of the statistics."""
     import threading
 
-    curves = [synth.serving_curve(k) for k in range(n_req)]
-    arrivals = synth.poisson_arrivals(0, n_req, rate)
+    if curves is None:
+        curves = [synth.serving_curve(k) for k in range(n_req)]
+    arrivals = (np.zeros(n_req) if not np.isfinite(rate)
+                else synth.poisson_arrivals(0, n_req, rate))
     ctx = qmi.Context(0)
     kw = dict(f_min=wl["f_min"], f_max=wl["f_max"], n_coarse=wl["n_coarse"], top_k=wl["top_k"],
               n_fine=wl["n_fine"])
@@ -69,7 +78,7 @@ def serving(qmi, synth, wl, st_, rate, n_req, max_batch, inflight):
     t0 = time.perf_counter()
 
     def submitter():
-        for k, c in enumerate(curves):
+        for k, c in enumerate(curves[:n_req]):
             delay = t0 + arrivals[k] - time.perf_counter()
             if delay > 0:
                 time.sleep(delay)
@@ -80,7 +89,7 @@ def serving(qmi, synth, wl, st_, rate, n_req, max_batch, inflight):
     th = threading.Thread(target=submitter)
     th.start()
     got = 0
-    deadline = t0 + arrivals[-1] + 120.0
+    deadline = t0 + arrivals[-1] + 120.0 + (n_req / 50.0 if not np.isfinite(rate) else 0.0)
     while got < n_req and time.perf_counter() < deadline:
         res, tags = ctx.poll(256, 2000)
         now = time.perf_counter()
@@ -93,9 +102,15 @@ def serving(qmi, synth, wl, st_, rate, n_req, max_batch, inflight):
     ctx.close()
     lat = (t_done - t_arr) * 1e3
     ok = np.isfinite(lat)
-    span = np.nanmax(t_done) - t0
-    return {"requests": n_req, "completed": int(ok.sum()), "arrival_rate_per_s": rate,
-            "p50_ms": float(np.percentile(lat[ok], 50)), "p99_ms": float(np.percentile(lat[ok], 99)),
+    ok[:warmup] = False
+    # Throughput over the measured requests: from the first measured arrival to the last
+    # completion.
+    t_first = t_arr[warmup] if warmup < n_req else t0
+    span = np.nanmax(t_done[warmup:]) - t_first
+    return {"requests": n_req, "warmup_requests": warmup, "completed": int(ok.sum()),
+            "arrival_rate_per_s": None if not np.isfinite(rate) else rate,
+            "p50_ms": float(np.percentile(lat[ok], 50)),
+            "p99_ms": float(np.percentile(lat[ok], 99)),
             "max_ms": float(np.max(lat[ok])), "throughput_per_s": float(ok.sum() / span),
             "max_batch": max_batch, "max_inflight": inflight,
             "lengths": "round(lognormal(ln 500, 0.5)) in [50, 2000]",
@@ -189,16 +204,21 @@ def main():
         ks = list(range(min(a.plain_sample, nc)))
         torch.cuda.synchronize()
         p0 = time.perf_counter()
+        call_ms = []
         for k in ks:
             lo, hi = int(batch.offsets[k]), int(batch.offsets[k + 1])
+            c0 = time.perf_counter()
             ctx.best_period_dev([0, hi - lo], T[lo:hi], Y[lo:hi], E[lo:hi], st_, **kw)
+            call_ms.append(1e3 * (time.perf_counter() - c0))
         torch.cuda.synchronize()
         pdt = time.perf_counter() - p0
         pitems = sum(float(n) * (n - 1) / 2.0 for n in np.diff(batch.offsets)[ks])
         bitems = sum(float(n) * (n - 1) / 2.0 for n in np.diff(batch.offsets))
         # Scale the sample to the batch by pair work, so that the ratio compares like with like.
         plain_value = nc / (pdt * bitems / pitems)
-        plain = {"value": plain_value, "sample_curves": len(ks), "speedup": value / plain_value}
+        plain = {"value": plain_value, "sample_curves": len(ks), "speedup": value / plain_value,
+                 "call_p50_ms": float(np.percentile(call_ms, 50)),
+                 "call_p99_ms": float(np.percentile(call_ms, 99))}
 
     cpu = None
     if a.cpu_sample > 0:
@@ -221,9 +241,27 @@ def main():
                                                  items_per_curve)}
 
     serve = None
-    if a.serve_requests > 0:
+    sweep = None
+    if a.serve_requests > 0 and a.serve_sweep:
+        n_req = a.serve_requests + a.serve_warmup
+        curves = [synth.serving_curve(k) for k in range(n_req)]
+        sat = serving(qmi, synth, wl, st_, float("inf"), n_req, a.serve_batch, a.serve_inflight,
+                      warmup=a.serve_warmup, curves=curves)
+        print("serving saturated: %.1f requests/s" % sat["throughput_per_s"], file=sys.stderr,
+              flush=True)
+        sweep = {"saturated": sat, "loads": []}
+        for load in [float(x) for x in a.serve_sweep.split(",")]:
+            r = serving(qmi, synth, wl, st_, load * sat["throughput_per_s"], n_req, a.serve_batch,
+                        a.serve_inflight, warmup=a.serve_warmup, curves=curves)
+            r["load"] = load
+            print("serving at %.2f of saturation: p50 %.1f ms p99 %.1f ms, %.1f requests/s"
+                  % (load, r["p50_ms"], r["p99_ms"], r["throughput_per_s"]), file=sys.stderr,
+                  flush=True)
+            sweep["loads"].append(r)
+        serve = min(sweep["loads"], key=lambda r: abs(r["load"] - 0.5))
+    elif a.serve_requests > 0:
         serve = serving(qmi, synth, wl, st_, a.serve_load * value, a.serve_requests,
-                        a.serve_batch, a.serve_inflight)
+                        a.serve_batch, a.serve_inflight, warmup=a.serve_warmup)
 
     line = {
         "metric": METRIC,
@@ -255,6 +293,7 @@ def main():
         "graph": graph,
         "plain": plain,
         "serving": serve,
+        "serving_sweep": sweep,
         "p99_ms": serve and serve["p99_ms"],
         "cpu_baseline": cpu,
     }

@@ -67,6 +67,10 @@ extern "C" {
 /* Arithmetic of the pair sums. */
 #define QMI_PREC_MIXED 0 /* FP64 fold + FP32 kernel values + FP32 short sums folded into FP64 */
 #define QMI_PREC_FP64 1  /* every step in FP64 */
+/* Negative control for precision studies, not for use: QMI_PREC_MIXED with the phase fold
+ * f t - rint(f t) taken in FP32 instead of FP64.  Over long baselines at high frequencies f t
+ * reaches 1e5 cycles, where an FP32 ulp is ~0.01 cycle, and the scores degrade accordingly. */
+#define QMI_PREC_FOLD32 2
 
 /* Discriminator output values. */
 #define QMI_NOT_PERIODIC 0

@@ -143,7 +143,8 @@ int check_kernel_params(qmi_ctx* ctx, const qmi_kernel_params* kp) {
         set_err(ctx, "sigma_y must be > 0 or a QMI_SIGMA_* rule (got %g)", kp->sigma_y);
         return QMI_EINVAL;
     }
-    if (kp->precision != QMI_PREC_MIXED && kp->precision != QMI_PREC_FP64) {
+    if (kp->precision != QMI_PREC_MIXED && kp->precision != QMI_PREC_FP64 &&
+        kp->precision != QMI_PREC_FOLD32) {
         set_err(ctx, "unknown precision %d", kp->precision);
         return QMI_EINVAL;
     }
@@ -453,12 +454,14 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
     }
     const int nvar = pair_variants<R>();
     int variant = 0;
-    if (ctx->tile > 0) variant = (int)std::min<int64_t>(ctx->tile - 1, nvar - 1);
+    const bool fold32 = kp->precision == QMI_PREC_FOLD32;
+    if (fold32) variant = kVariantFold32;
+    else if (ctx->tile > 0) variant = (int)std::min<int64_t>(ctx->tile - 1, nvar - 1);
     else if (!fp64 && ctx->tuned[bucket] >= 0) variant = ctx->tuned[bucket];
     double group_items = 0.0;
     for (int32_t i = 0; i < nc; ++i)
         if (cp[i].status == QMI_OK) group_items += 0.5 * cp[i].n * (cp[i].n - 1.0) * (double)F1;
-    const bool tune_now = !fp64 && ctx->tile == 0 && ctx->tuned[bucket] < 0 && nvar > 1 &&
+    const bool tune_now = !fp64 && !fold32 && ctx->tile == 0 && ctx->tuned[bucket] < 0 && nvar > 1 &&
                           group_items > 2e9;
     ctx->stats.pair_variant = variant;
 

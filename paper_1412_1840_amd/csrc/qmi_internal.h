@@ -14,6 +14,7 @@ namespace qmi {
 constexpr int kLanes = 64;
 constexpr int kWaves = 8;
 constexpr int kThreads = kWaves * kLanes;
+constexpr int kXcds = 8;    // accelerator complex dies of an MI355X, one L2 each
 constexpr int kPass = 256;  // rows per pass; the K-table permutation is defined on it
 constexpr int kChunk = 64;  // columns per LDS chunk
 
@@ -103,7 +104,9 @@ hipError_t launch_gram_finalize(hipStream_t st, CurveParams* cp, int n_curves, c
                                 double* rp);
 template <typename R>
 hipError_t launch_ksum(hipStream_t st, const CurveParams* cp, int n_curves, const R* K, R* ks);
-// Pair-kernel variants: ids 0 .. pair_variants<R>() - 1 (0 is the default).
+// Pair-kernel variants: ids 0 .. pair_variants<R>() - 1 (0 is the default), and for R = float
+// kVariantFold32, the shape of variant 0 with the phase fold in FP32 (a precision control).
+constexpr int kVariantFold32 = -1;
 template <typename R>
 int pair_variants();
 template <typename R>

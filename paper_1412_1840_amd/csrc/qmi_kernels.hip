@@ -309,15 +309,22 @@ __device__ __forceinline__ void sincos_2pi_reduced(double p, double& sn, double&
 // its constant (sin^2 of half the angle between the warp points u_f(t_i), u_f(t_j), whose chord is
 // 2 |sin|).  d is formed from a difference of products, so it is exact to rounding when the two
 // phases coincide and the kernel value is then exactly 1.
-template <typename R>
+template <typename R, bool FOLD32 = false>
 struct Warp;
 
-template <>
-struct Warp<float> {
+template <bool FOLD32>
+struct Warp<float, FOLD32> {
     using V = float2;
     __device__ __forceinline__ static V at(double f, double t, double scale) {
-        const double n = rint(f * t);
-        const double p = fma(f, t, -n);
+        double p;
+        if constexpr (FOLD32) {
+            // Precision control only: the fold in FP32 (one rounding of f t to FP32).
+            const float x = (float)f * (float)t;
+            p = (double)(x - rintf(x));
+        } else {
+            const double n = rint(f * t);
+            p = fma(f, t, -n);
+        }
         double sn, cs;
         sincos_2pi_reduced(0.5 * p, sn, cs);  // sin(pi p), cos(pi p)
         return make_float2((float)(cs * scale), (float)(sn * scale));
@@ -326,7 +333,7 @@ struct Warp<float> {
 };
 
 template <>
-struct Warp<double> {
+struct Warp<double, false> {
     using V = double2;
     __device__ __forceinline__ static V at(double f, double t, double scale) {
         const double n = rint(f * t);
@@ -366,32 +373,40 @@ __device__ __forceinline__ void pair_term(R hc, R hs, R ux, R uy, R moff, R k, R
 // Variants (chosen by the host autotuner): WPE is the occupancy target in waves per SIMD (2: the
 // registers of 2 waves, no spills; 4: at most 128 VGPRs, so two workgroups share a CU), CH the
 // columns per LDS chunk.
-template <typename R, int WPE, int CH>
+template <typename R, int WPE, int CH, bool FOLD32 = false>
 __global__ void __launch_bounds__(kThreads, WPE)
 pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ order,
              FreqPlan fp, const double* __restrict__ t_all, const R* __restrict__ K_all,
              const double* __restrict__ rd_all, const double* __restrict__ rp_all,
-             const R* __restrict__ ks_all, PairOut out) {
-    using W = Warp<R>;
+             const R* __restrict__ ks_all, int n_work, PairOut out) {
+    using W = Warp<R, FOLD32>;
     using V = typename W::V;
     constexpr int ROWS = rows_per_wave<R>();
     constexpr int PASS = kWaves * ROWS;
     constexpr int GRP = 4;  // rows skipped together in the diagonal region
     __shared__ V ph[2][CH][kLanes];
+    __shared__ double fq[kWaves][kLanes];  // the lane's frequency, re-read where the warp is formed
 
     const int lane = threadIdx.x & 63;
     const int w = uniform((int)(threadIdx.x >> 6));
     const int tiles = (fp.count + kLanes - 1) / kLanes;
-    const int rank = blockIdx.x / tiles;
-    const int tile = blockIdx.x - rank * tiles;
+    // The dispatcher deals blocks to the XCDs round robin (block b runs on XCD b mod kXcds), and
+    // each XCD has its own L2.  Give every XCD whole curves (work ranks x, x + kXcds, ...) with
+    // their frequency tiles in consecutive blocks, so that a curve's K table is fetched into one
+    // L2 only.  The grid is padded to a multiple of kXcds curves.
+    const int xcd = (int)(blockIdx.x % kXcds);
+    const int seq = (int)(blockIdx.x / kXcds);
+    const int rank = (seq / tiles) * kXcds + xcd;
+    const int tile = seq - (seq / tiles) * tiles;
+    if (rank >= n_work) return;
     const int c = order[rank];
     const CurveParams P = cp[c];
     const int slot = tile * kLanes + lane;
     bool active;
     const double f = slot_freq(fp, c, slot, active);
-    const int64_t obase = (int64_t)c * fp.count + slot;
 
     if (P.status != 0) {
+        const int64_t obase = (int64_t)c * fp.count + slot;
         if (active && w == 0) {
             out.score[obase] = NAN;
             if (out.score2) out.score2[obase] = NAN;
@@ -407,11 +422,14 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
     const int n = P.n;
     const double* t = t_all + P.off;
     const double* rr = rd_all + P.off;
-    const double scale = sqrt(sqrt(2.0 * kLog2e) / P.sigma_t);
+    const double scale = uniform(sqrt(sqrt(2.0 * kLog2e) / P.sigma_t));
     const R zero = R(0);
     const R pinf = uniform((R)INFINITY);
 
-    double SJ = 0.0, ST = 0.0, SCa = 0.0, SCb = 0.0;
+    double SJ = 0.0, ST = 0.0, SC = 0.0;  // SC = SCa + SCb
+    // Kept in LDS rather than in two registers across the column loops (each wave reads back only
+    // what it wrote).
+    fq[w][lane] = f;
 
     for (int base = 0; base < n; base += PASS) {
         // This wave's rows: base + w + kWaves * m, m < nrows.
@@ -420,7 +438,7 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
 #pragma unroll
         for (int m = 0; m < ROWS; ++m) {
             const int i = base + w + kWaves * m;
-            V u = (m < nrows) ? W::at(f, t[i], scale) : V{R(0), R(0)};
+            V u = (m < nrows) ? W::at(fq[w][lane], t[i], scale) : V{R(0), R(0)};
             ci[m] = u.x;
             si[m] = u.y;
             G[m] = R(0);
@@ -434,7 +452,7 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
         auto stage = [&](int j0, int buf) {
             for (int q = w; q < CH; q += kWaves) {
                 const int j = j0 + q;
-                ph[buf][q][lane] = (j < n) ? W::at(f, t[j], scale) : V{R(0), R(0)};
+                ph[buf][q][lane] = (j < n) ? W::at(fq[w][lane], t[j], scale) : V{R(0), R(0)};
             }
         };
         stage(base, 0);
@@ -467,7 +485,7 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
                     const double Td = (double)Tq;
                     ST += Td;
                     SJ += (double)(Jq - ksj);
-                    SCb = fma(Td, rj, SCb);
+                    SC = fma(Td, rj, SC);
                 }
             } else {
                 for (int q = 0; q < jend; ++q) {
@@ -500,7 +518,7 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
                     const double Td = (double)Tq;
                     ST += Td;
                     SJ += (double)(Jq - ksb[j]);
-                    SCb = fma(Td, rr[j], SCb);
+                    SC = fma(Td, rr[j], SC);
                 }
             }
             // Row sums of this chunk, weighted by the FP64 row sums r_i.
@@ -509,7 +527,7 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
             for (int m = 0; m < ROWS; ++m) rk[m] = rpb[m];
 #pragma unroll
             for (int m = 0; m < ROWS; ++m) {
-                SCa = fma((double)G[m], rk[m], SCa);
+                SC = fma((double)G[m], rk[m], SC);
                 G[m] = R(0);
             }
             __syncthreads();
@@ -518,23 +536,22 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
 
     // Combine the waves' partial sums in wave order (deterministic), then the epilogue.
     double* red = reinterpret_cast<double*>(&ph[0][0][0]);
-    red[(w * kLanes + lane) * 4 + 0] = SJ;
-    red[(w * kLanes + lane) * 4 + 1] = ST;
-    red[(w * kLanes + lane) * 4 + 2] = SCa;
-    red[(w * kLanes + lane) * 4 + 3] = SCb;
+    red[(w * kLanes + lane) * 3 + 0] = SJ;
+    red[(w * kLanes + lane) * 3 + 1] = ST;
+    red[(w * kLanes + lane) * 3 + 2] = SC;
     __syncthreads();
     if (w != 0 || !active) return;
-    SJ = ST = SCa = SCb = 0.0;
+    SJ = ST = SC = 0.0;
     for (int v = 0; v < kWaves; ++v) {
-        SJ += red[(v * kLanes + lane) * 4 + 0];
-        ST += red[(v * kLanes + lane) * 4 + 1];
-        SCa += red[(v * kLanes + lane) * 4 + 2];
-        SCb += red[(v * kLanes + lane) * 4 + 3];
+        SJ += red[(v * kLanes + lane) * 3 + 0];
+        ST += red[(v * kLanes + lane) * 3 + 1];
+        SC += red[(v * kLanes + lane) * 3 + 2];
     }
+    const int64_t obase = (int64_t)c * fp.count + slot;
     const double N = (double)n;
     const double VJ = P.A * (N * P.bk + 2.0 * (P.sjc + SJ)) / (N * N);
     const double IPt = P.A * (N + 2.0 * ST) / (N * N);
-    const double VC = P.A * (P.rsum + SCa + SCb) / (N * N * N);
+    const double VC = P.A * (P.rsum + SC) / (N * N * N);
     const double VM = P.ipy * IPt;
     const double q = log(VJ) + log(VM) - 2.0 * log(VC);
     const double nckp = sqrt(N * P.sigma_t) / P.ipy * (VJ - VM);
@@ -787,12 +804,13 @@ int pair_variants() {
 template int pair_variants<float>();
 template int pair_variants<double>();
 
-template <typename R, int WPE, int CH>
+template <typename R, int WPE, int CH, bool FOLD32 = false>
 static hipError_t launch_pairs_v(hipStream_t st, const CurveParams* cp, const int32_t* order,
                                  unsigned grid, const FreqPlan& fp, const double* t, const R* K,
                                  const double* r, const double* rp, const R* ks,
-                                 const PairOut& out) {
-    pairs_kernel<R, WPE, CH><<<grid, kThreads, 0, st>>>(cp, order, fp, t, K, r, rp, ks, out);
+                                 int n_work, const PairOut& out) {
+    pairs_kernel<R, WPE, CH, FOLD32><<<grid, kThreads, 0, st>>>(cp, order, fp, t, K, r, rp, ks, n_work,
+                                                        out);
     return hipGetLastError();
 }
 
@@ -803,17 +821,23 @@ hipError_t launch_pairs(hipStream_t st, const CurveParams* cp, const int32_t* or
                         int variant) {
     if (n_work_curves <= 0 || fp.count <= 0) return hipSuccess;
     const int tiles = (fp.count + kLanes - 1) / kLanes;
-    const unsigned grid = (unsigned)((int64_t)tiles * n_work_curves);
+    const int64_t padded = (int64_t)(n_work_curves + kXcds - 1) / kXcds * kXcds;
+    const unsigned grid = (unsigned)(padded * tiles);
+    const int nw = n_work_curves;
     if constexpr (sizeof(R) == 4) {
         switch (variant) {
-            case 1: return launch_pairs_v<R, 4, 64>(st, cp, order, grid, fp, t, K, r, rp, ks, out);
-            case 2: return launch_pairs_v<R, 2, 32>(st, cp, order, grid, fp, t, K, r, rp, ks, out);
-            case 3: return launch_pairs_v<R, 4, 32>(st, cp, order, grid, fp, t, K, r, rp, ks, out);
-            default: return launch_pairs_v<R, 2, 64>(st, cp, order, grid, fp, t, K, r, rp, ks, out);
+            case kVariantFold32:
+                return launch_pairs_v<R, 2, 64, true>(st, cp, order, grid, fp, t, K, r, rp, ks, nw,
+                                                      out);
+            case 1: return launch_pairs_v<R, 4, 64>(st, cp, order, grid, fp, t, K, r, rp, ks, nw, out);
+            case 2: return launch_pairs_v<R, 2, 32>(st, cp, order, grid, fp, t, K, r, rp, ks, nw, out);
+            case 3: return launch_pairs_v<R, 4, 32>(st, cp, order, grid, fp, t, K, r, rp, ks, nw, out);
+            default: return launch_pairs_v<R, 2, 64>(st, cp, order, grid, fp, t, K, r, rp, ks, nw,
+                                                     out);
         }
     } else {
         (void)variant;
-        return launch_pairs_v<R, 2, 32>(st, cp, order, grid, fp, t, K, r, rp, ks, out);
+        return launch_pairs_v<R, 2, 32>(st, cp, order, grid, fp, t, K, r, rp, ks, nw, out);
     }
 }
 template hipError_t launch_pairs<float>(hipStream_t, const CurveParams*, const int32_t*, int,

@@ -30,6 +30,7 @@ SCORE_QMI = 0
 SCORE_NCKP = 1
 PREC_MIXED = 0
 PREC_FP64 = 1
+PREC_FOLD32 = 2  # precision control only: phase fold in FP32
 OPT_USE_GRAPH = 1
 OPT_TILE = 2
 NOT_PERIODIC, PERIODIC, UNDECIDED = 0, 1, 255

@@ -1,0 +1,139 @@
+"""Precision study on the long-baseline workload: 7000-day baselines with the seasonal cadence,
+N = 1000, periods log-uniform in [0.05, 10] d, frequencies up to 20 1/d, so that f t reaches
+1.4e5 cycles.  Three arithmetic modes of the GPU path are compared with the FP64 oracle:
+
+* QMI_PREC_FP64   - every step in FP64;
+* QMI_PREC_MIXED  - FP64 phase fold, FP32 kernel values and short FP32 sums folded into FP64,
+                    FP64 epilogue (the production mode);
+* QMI_PREC_FOLD32 - the mixed mode with the fold in FP32, a negative control that shows why the
+                    fold is kept in FP64.
+
+For each curve, width sigma_t in {0.3, 0.1, 0.6} and mode: the per-frequency QMI error
+|dQMI| / max(|QMI_ref|, 1e-3 max |QMI_ref|) and the relative errors of V_J, IP_t and V_C, on a
+seeded sample of frequencies (random points of the 20 000-point coarse grid on [1e-3, 20] plus a
+window around the generating frequency of periodic curves).  Then the best period of the full
+coarse-to-fine search against the stored oracle search (tests/golden/long_baseline_oracle.json).
+
+QMI_PRECISION_CURVES sets the number of curves (default 16; the full study uses 128), and
+QMI_REPORT_DIR, when set, receives precision_long_baseline.json with every statistic.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1412_1840_amd import qmi, synth
+
+pytestmark = pytest.mark.gpu
+
+QMI_TOL = 1e-4
+V_RTOL = 2e-6
+FP64_TOL = 1e-10
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _freq_sample(k, c, n_random=224, n_window=32):
+    wl = synth.WORKLOADS["long_baseline"]
+    grid = O.linear_grid(wl["f_min"], wl["f_max"], wl["n_coarse"])
+    rng = np.random.default_rng([4242, k])
+    idx = np.sort(rng.choice(len(grid), n_random + (0 if c.periodic else n_window), replace=False))
+    f = list(grid[idx])
+    if c.periodic:
+        f0 = 1.0 / c.period
+        half = 2.0 * (grid[1] - grid[0])
+        f += list(np.linspace(f0 - half, f0 + half, n_window))
+    return np.asarray(f)
+
+
+def _errors(sc, ips, ref):
+    rq = O.qmi(ref)
+    den = np.maximum(np.abs(rq), 1e-3 * np.max(np.abs(rq)))
+    q = np.abs(sc - rq) / den
+    v = [np.abs(ips[:, i] / r - 1.0) for i, r in enumerate((ref.vj, ref.ipt, ref.vc))]
+    return q, v
+
+
+def test_long_baseline_precision_modes():
+    n_curves = int(os.environ.get("QMI_PRECISION_CURVES", "16"))
+    curves = [synth.long_baseline_curve(k) for k in range(n_curves)]
+    b = synth.pack(curves)
+    freq = [_freq_sample(k, c) for k, c in enumerate(curves)]
+    widths = (0.3, 0.1, 0.6)
+    modes = (("fp64", qmi.PREC_FP64), ("mixed", qmi.PREC_MIXED), ("fold32", qmi.PREC_FOLD32))
+    report = {"workload": "long_baseline", "n_curves": n_curves, "n": 1000,
+              "freqs_per_curve": int(len(freq[0])), "sigma_y": "silverman", "stats": {}}
+    # The per-curve frequency lists differ, so the GPU runs one periodogram per curve and width.
+    with qmi.Context(0) as ctx:
+        for st in widths:
+            refs = [O.information_potentials(c.t, c.y, st, O.silverman_sigma(c.y), f, mode=1)
+                    for c, f in zip(curves, freq)]
+            for name, prec in modes:
+                qerr, verr = [], [[], [], []]
+                for k, c in enumerate(curves):
+                    sc, ips, _, s = ctx.periodogram([0, c.n], c.t, c.y, c.e, freq[k], st,
+                                                    precision=prec, want_ips=True)
+                    assert s[0] == 0
+                    q, v = _errors(sc[0], ips[0], refs[k])
+                    qerr.append(q)
+                    for i in range(3):
+                        verr[i].append(v[i])
+                q = np.concatenate(qerr)
+                vs = [np.concatenate(x) for x in verr]
+                rec = {"qmi_max": float(q.max()), "qmi_p999": float(np.quantile(q, 0.999)),
+                       "qmi_median": float(np.median(q)),
+                       "vj_max": float(vs[0].max()), "ipt_max": float(vs[1].max()),
+                       "vc_max": float(vs[2].max()), "points": int(q.size)}
+                report["stats"]["%s/sigma_t=%g" % (name, st)] = rec
+                print("sigma_t %.1f %-6s QMI floor-rel max %.2e p99.9 %.2e median %.2e | "
+                      "V_J %.2e IP_t %.2e V_C %.2e" % (st, name, rec["qmi_max"], rec["qmi_p999"],
+                                                       rec["qmi_median"], rec["vj_max"],
+                                                       rec["ipt_max"], rec["vc_max"]))
+    s = report["stats"]
+    for st in widths:
+        fp64, mixed, fold32 = (s["%s/sigma_t=%g" % (m, st)] for m in ("fp64", "mixed", "fold32"))
+        assert fp64["qmi_max"] <= FP64_TOL
+        assert max(fp64["vj_max"], fp64["ipt_max"], fp64["vc_max"]) <= 1e-11
+        assert mixed["qmi_max"] <= QMI_TOL
+        assert max(mixed["vj_max"], mixed["ipt_max"], mixed["vc_max"]) <= V_RTOL
+        # The control must be far outside the bar: the FP64 fold is what keeps the mixed path in.
+        assert fold32["qmi_max"] > 100 * QMI_TOL
+    out = os.environ.get("QMI_REPORT_DIR")
+    if out:
+        os.makedirs(out, exist_ok=True)
+        with open(os.path.join(out, "precision_long_baseline.json"), "w") as f:
+            json.dump(report, f, indent=1)
+
+
+def test_long_baseline_best_period_matches_oracle_full_search():
+    """Full-size search on the long-baseline workload (20 000 coarse + 10 x 1000 refined
+    frequencies on [1e-3, 20] 1/d) against the stored FP64 oracle search, for the mixed and FP64
+    modes; the FP32-fold control is reported, not asserted."""
+    path = os.path.join(HERE, "golden", "long_baseline_oracle.json")
+    gold = json.load(open(path))
+    recs = gold["curves"]
+    curves = [synth.long_baseline_curve(r["k"]) for r in recs]
+    b = synth.pack(curves)
+    with qmi.Context(0) as ctx:
+        for name, prec in (("mixed", qmi.PREC_MIXED), ("fp64", qmi.PREC_FP64),
+                           ("fold32", qmi.PREC_FOLD32)):
+            res, _ = ctx.best_period(b.offsets, b.t, b.y, b.e, gold["sigma_t"],
+                                     precision=prec, **gold["search"])
+            same, flat, bad = 0, 0, []
+            for r, c, g in zip(res, curves, recs):
+                assert r["status"] == 0
+                if (r["coarse_index"] == g["coarse_index"] and r["fine_index"] == g["fine_index"]):
+                    assert r["f_best"] == g["f_best"]
+                    same += 1
+                    continue
+                q = O.qmi(O.information_potentials(c.t, c.y, gold["sigma_t"], g["sigma_y"],
+                                                   [r["f_best"]]))[0]
+                if g["best_gap"] <= 1e-5 * abs(g["score"]) and q >= g["score"] * (1 - 1e-5):
+                    flat += 1
+                else:
+                    bad.append((g["k"], g["fine_index"], int(r["fine_index"])))
+            print("long baseline %-6s: %d of %d identical best indices, %d flat-maximum ties, "
+                  "%d different %s" % (name, same, len(recs), flat, len(bad), bad))
+            if name != "fold32":
+                assert not bad, (name, bad)
