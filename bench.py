@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--tile", type=int, default=0,
                     help="force pair-kernel variant k-1 (0: autotuned)")
     ap.add_argument("--no-graph-check", action="store_true")
+    ap.add_argument("--bands-steps", type=int, default=2,
+                    help="timed calls of the bands-method front end on the same batch (0: skip)")
     return ap.parse_args()
 
 
@@ -115,6 +117,37 @@ def serving(qmi, synth, wl, st_, rate, n_req, max_batch, inflight, warmup=0, cur
             "max_batch": max_batch, "max_inflight": inflight,
             "lengths": "round(lognormal(ln 500, 0.5)) in [50, 2000]",
             "bad_status": int(np.sum(status != 0))}
+
+
+def synth_curve(workload, k):
+    from paper_1412_1840_amd import synth
+
+    return {"survey_batch": synth.survey_batch_curve, "long_baseline": synth.long_baseline_curve,
+            "serving_stream": synth.serving_curve,
+            "survey_stream": synth.survey_stream_curve}[workload](k)
+
+
+def measured_traffic(workload, n_curves, variant):
+    """HBM bytes per pair-kernel launch from the committed counter summary, or None unless the
+    counters were taken on this workload, this variant and the current kernel source."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "pairs_kernel_survey_batch_4096_traffic.txt")
+    if workload != "survey_batch" or n_curves != 4096 or not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for name in ("qmi_kernels.hip", "qmi_internal.h"):
+        with open(os.path.join(ROOT, "paper_1412_1840_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    digest = h.hexdigest()
+    if kv.get("kernel_source_sha256") != digest or int(kv.get("variant", -99)) != variant:
+        return None
+    return float(kv["bytes_per_launch"])
 
 
 def valu_probe():
@@ -240,6 +273,49 @@ def main():
                          "the workload needs" % (len(cs), len(fr), citems, cdt, citems / cdt,
                                                  items_per_curve)}
 
+    # Bands-method front end (Sec. 3.1: 3 bands x 150 trial frequencies instead of the coarse
+    # grid and refinement) on the same batch, and the period recovery of both front ends against
+    # the generator's truth: a periodic curve's period counts as recovered when the best frequency
+    # lies within half a Fourier resolution element, 1 / (2 T), of the generating one.
+    bands = None
+    if a.bands_steps > 0 and a.workload in ("survey_batch", "long_baseline", "serving_stream",
+                                             "survey_stream"):
+        hb = synth.make_batch(a.workload, range(a.n_curves))
+        bctx = qmi.Context(0)
+        bctx.bands_best_period(hb.offsets, hb.t, hb.y, hb.e, st_)  # warm-up (and autotune)
+        b0 = time.perf_counter()
+        bitems = 0.0
+        for _ in range(a.bands_steps):
+            bres, _, _ = bctx.bands_best_period(hb.offsets, hb.t, hb.y, hb.e, st_)
+            bitems += bctx.stats()["pair_items"]
+        bdt = time.perf_counter() - b0
+        bctx.close()
+        truth = [synth_curve(a.workload, k) for k in range(nc)]
+        per = [k for k, c in enumerate(truth) if c.periodic]
+
+        def recovered(r, k):
+            c = truth[k]
+            span = float(c.t.max() - c.t.min())
+            return bool(abs(r["f_best"][k] - 1.0 / c.period) <= 0.5 / span)
+
+        in_range = [k for k in per if 1.0 / truth[k].period >= 0.00125 and
+                    1.0 / truth[k].period <= 3.0]
+        bands = {"value": nc * a.bands_steps / bdt, "unit": "lightcurves/s",
+                 "ms_per_step": 1e3 * bdt / a.bands_steps,
+                 "host_inputs": True,
+                 "gpairs_per_s": bitems / bdt / 1e9,
+                 "trials_per_curve": "3 bands x 150 local maxima of the spectral window on 30000 "
+                                     "points of [0.00125, 3] 1/d",
+                 "periodic_curves": len(per),
+                 "recovered_bands": sum(recovered(bres, k) for k in per) / max(len(per), 1),
+                 "recovered_coarse_to_fine": sum(recovered(res, k) for k in per)
+                 / max(len(per), 1),
+                 "periodic_in_bands_range": len(in_range),
+                 "recovered_bands_in_range": sum(recovered(bres, k) for k in in_range)
+                 / max(len(in_range), 1),
+                 "recovered_coarse_to_fine_in_range": sum(recovered(res, k) for k in in_range)
+                 / max(len(in_range), 1)}
+
     serve = None
     sweep = None
     if a.serve_requests > 0 and a.serve_sweep:
@@ -284,13 +360,15 @@ def main():
         "gpairs_per_s": items / a.steps / (dt / a.steps) / 1e9,
         "roofline": {"bound": "alu", "achieved": achieved / 1e9, "peak": PEAK_ITEMS_PER_S / 1e9,
                      "unit": "G pair*freq items/s", "frac": achieved / PEAK_ITEMS_PER_S,
-                     "traffic": None,
+                     "traffic": measured_traffic(a.workload, nc, variant),
+                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated)",
                      "kernel": "pairs_kernel<float>", "variant": variant, "launches": launches,
                      "avg_launch_ms": pair_ms / max(launches, 1),
                      "probe_pair_items_per_s": probe and probe.get("pair_items_per_s"),
                      "probe_exp_per_s": probe and probe.get("exp_per_s"),
                      "probe_fma_per_s": probe and probe.get("fma_per_s")},
         "graph": graph,
+        "bands": bands,
         "plain": plain,
         "serving": serve,
         "serving_sweep": sweep,

@@ -55,6 +55,8 @@ extern "C" {
 /* Limits. */
 #define QMI_MAX_N 8192  /* samples per curve */
 #define QMI_MAX_TOPK 32 /* refined peaks per curve */
+#define QMI_MAX_BANDS 32    /* magnitude bands of the bands method */
+#define QMI_MAX_TRIALS 1024 /* trial frequencies per band of the bands method */
 
 /* sigma_y rules (qmi_kernel_params.sigma_y <= 0 selects a rule). */
 #define QMI_SIGMA_SILVERMAN (-1.0)  /* 0.9 min(s, IQR/1.34) N^(-1/5); s on N-1, linear quartiles */
@@ -119,7 +121,30 @@ typedef struct {
     int32_t score;
 } qmi_search;
 
-/* Per-curve result of qmi_best_period. */
+/*
+ * Trial frequencies by the bands method (Sec. 3.1), for qmi_bands_best_period.  Per curve, samples
+ * are taken in time order (stable) and split by magnitude rank into n_bands equal-count bands
+ * (rank r goes to band floor(n_bands r / N)).  Band j is ranked by D_j = sum of |d_i| over its
+ * samples i, d_i = (y_{i+1} - y_i) / (t_{i+1} - t_i) (summed in time order; a pair of equal times
+ * adds nothing); the n_keep bands with the largest D_j (ties to the lower band) are kept.  For
+ * each kept band the spectral window S_j(f) = |sum_{i in band} exp(2 pi i f t_i)|^2 is evaluated on
+ * the grid f_k = f_lo + k * ((f_hi - f_lo) / (n_grid - 1)) (FP64), and its n_trials highest local
+ * maxima (the local-maximum and tie rules of qmi_search), leaving out any with |1/f_k - 1| < 1e-4
+ * (the one-day sampling period), are the band's trial frequencies.  The paper uses n_bands 10,
+ * n_keep 3, n_trials 150 and the grid [0.00125, 3] 1/d; its grid density is not stated.
+ * Requirements: 0 < f_lo < f_hi, 2 <= n_grid <= 2^24, 1 <= n_keep <= n_bands <= QMI_MAX_BANDS,
+ * 1 <= n_trials <= QMI_MAX_TRIALS, score one of QMI_SCORE_*.
+ */
+typedef struct {
+    double f_lo, f_hi;
+    int32_t n_grid;
+    int32_t n_bands, n_keep, n_trials;
+    int32_t score;
+    int32_t reserved;
+} qmi_bands;
+
+/* Per-curve result of qmi_best_period (and of qmi_bands_best_period, which uses the integer
+ * fields as noted in its description). */
 typedef struct {
     double f_best;      /* 1/day */
     double period;      /* 1 / f_best, days */
@@ -214,6 +239,26 @@ int qmi_periodogram_dev(qmi_ctx *ctx, const qmi_batch *batch, const qmi_kernel_p
                         double *ips_out, double *ip_y_out, int32_t *status_out);
 int qmi_best_period_dev(qmi_ctx *ctx, const qmi_batch *batch, const qmi_kernel_params *kp,
                         const qmi_search *search, qmi_result *out, double *coarse_out);
+
+/*
+ * Best period over the trial frequencies of the bands method (Sec. 3.1 followed by the score of
+ * Sec. 3): the score at each of the n_keep * n_trials trial frequencies of every curve, and the
+ * best (highest score, ties to the lower frequency, then the earlier trial).  Trials are listed band
+ * by band in rank order, each band's maxima by rank; a band with fewer local maxima leaves its
+ * remaining entries empty (NaN).
+ *   out          host, [n_curves]; f_best, period, score, score_qmi, score_nckp, sigma_y, psnr,
+ *                n and status as for qmi_best_period; coarse_index = the best trial's position in
+ *                the list, peak_rank = its band's rank, fine_index = its rank inside the band,
+ *                coarse_argmax = its index on the spectral-window grid, n_peaks = the number of
+ *                trials found, coarse_best = NaN
+ *   trials_out   nullable host, [n_curves * n_keep * n_trials] trial frequencies (NaN: empty)
+ *   scores_out   nullable host, same shape: the score at each trial (NaN: empty)
+ * Needs per curve about n_keep * n_grid * 8 bytes of device memory for the spectral windows, in
+ * addition to the pair sums' tables.
+ */
+int qmi_bands_best_period(qmi_ctx *ctx, const qmi_batch *batch, const qmi_kernel_params *kp,
+                          const qmi_bands *bands, qmi_result *out, double *trials_out,
+                          double *scores_out);
 
 /*
  * Periodic / non-periodic decision (Sec. 4.1): for curve k with status QMI_OK, pSNR p (psnr[k] if

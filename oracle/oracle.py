@@ -390,3 +390,99 @@ def calibrate_thresholds(scores: Sequence[float], psnrs: Sequence[float],
                 best = (f, float(c), p, r)
         fs.append(best[0]); th.append(best[1]); ps.append(best[2]); rs.append(best[3])
     return {"th": th, "f1": fs, "precision": ps, "recall": rs}
+
+
+# ------------------------------------------------------------------------------------------
+# Trial frequencies by the bands method (Sec. 3.1) and the best period over them
+# ------------------------------------------------------------------------------------------
+# Readings where the paper leaves points open (the HIP library implements the same ones):
+# * samples are taken in time order (stable: equal times keep their input order);
+# * the derivative d_i = (y_{i+1} - y_i) / (t_{i+1} - t_i) belongs to sample i; a pair with equal
+#   times contributes nothing;
+# * the 10 equal-count bands split the samples by magnitude rank (stable in time order): sample
+#   of rank r is in band floor(10 r / N); D_j sums |d_i| in time order;
+# * bands are ranked by D_j descending, ties to the lower band;
+# * the spectral-window grid is linear with n_grid points (30 000 by default: spacing ~1e-4 1/d,
+#   about a quarter of the Fourier resolution of a 2500-day baseline);
+# * the N_t highest local maxima of S_j use the local-maximum and tie rules of the search; a
+#   maximum whose period satisfies |P - 1| < 1e-4 is dropped before the N_t are counted;
+# * the trial list is band by band in rank order, maxima by rank (duplicates across bands kept);
+# * the best trial is the highest score, ties to the lower frequency, then the earlier trial.
+
+BANDS_F_LO = 0.00125
+BANDS_F_HI = 3.0
+BANDS_GRID = 30000
+
+
+def bands_ranked(t, y, n_bands: int = 10) -> Tuple[np.ndarray, List[np.ndarray], List[float]]:
+    """Time-ordered samples, the band members (indices into the time order, increasing) and D_j.
+
+    Returns (order, members, D) where members[j] and D[j] belong to band j (j = 0 .. n_bands-1;
+    band 0 holds the smallest magnitudes)."""
+    t = np.asarray(t, np.float64)
+    y = np.asarray(y, np.float64)
+    n = len(t)
+    order = np.argsort(t, kind="stable")
+    ts, ys = t[order], y[order]
+    rank = np.empty(n, np.int64)
+    rank[np.argsort(ys, kind="stable")] = np.arange(n)
+    band = (rank * n_bands) // n
+    D = [0.0] * n_bands
+    for i in range(n - 1):
+        dt = ts[i + 1] - ts[i]
+        if dt != 0.0:
+            D[int(band[i])] += abs((ys[i + 1] - ys[i]) / dt)
+    members = [np.nonzero(band == j)[0] for j in range(n_bands)]
+    return order, members, D
+
+
+def spectral_window(times: np.ndarray, freqs: np.ndarray) -> np.ndarray:
+    """S(f) = |sum_i exp(2 pi i f t_i)|^2 (Sec. 3.1, the spectral window of the band's times)."""
+    x = np.outer(np.asarray(freqs, np.float64), np.asarray(times, np.float64))
+    p = x - np.rint(x)  # the phase in cycles; exp(2 pi i x) = exp(2 pi i p)
+    c = np.cos(2.0 * np.pi * p).sum(axis=1)
+    s = np.sin(2.0 * np.pi * p).sum(axis=1)
+    return c * c + s * s
+
+
+def bands_trial_frequencies(t, y, n_keep: int = 3, n_trials: int = 150,
+                            f_lo: float = BANDS_F_LO, f_hi: float = BANDS_F_HI,
+                            n_grid: int = BANDS_GRID, n_bands: int = 10) -> Dict[str, object]:
+    """The N_b N_t trial frequencies of the bands method (Sec. 3.1)."""
+    order, members, D = bands_ranked(t, y, n_bands)
+    ts = np.asarray(t, np.float64)[order]
+    ranked = sorted(range(n_bands), key=lambda j: (-D[j], j))[:n_keep]
+    grid = linear_grid(f_lo, f_hi, n_grid)
+    trials, per_band = [], []
+    for j in ranked:
+        S = spectral_window(ts[members[j]], grid)
+        peaks = [k for k in local_maxima(S) if not abs(1.0 / grid[k] - 1.0) < 1e-4]
+        peaks.sort(key=lambda k: (-S[k], k))
+        kept = peaks[:n_trials]
+        per_band.append(kept)
+        trials += [float(grid[k]) for k in kept]
+    return {"bands": ranked, "D": D, "grid_index": per_band, "freqs": np.array(trials)}
+
+
+def bands_best_period(t, y, e, sigma_t: float, sigma_y_rule: float, n_keep: int = 3,
+                      n_trials: int = 150, score: int = SCORE_QMI, n_grid: int = BANDS_GRID,
+                      n_threads: int = 0) -> Dict[str, object]:
+    """The score at every trial frequency and the best trial (Sec. 3.1 followed by Sec. 3)."""
+    tr = bands_trial_frequencies(t, y, n_keep, n_trials, n_grid=n_grid)
+    f = tr["freqs"]
+    sy = sigma_y_of(np.asarray(y, np.float64), None if e is None else np.asarray(e, np.float64),
+                    sigma_y_rule)
+    if len(f) == 0:
+        return dict(tr, scores=np.zeros(0), best=-1, f_best=math.nan, score=math.nan, sigma_y=sy)
+    ips = information_potentials(t, y, sigma_t, sy, f, 1, n_threads)
+    q = score_of(ips, score)
+    best = None
+    for i in range(len(f)):
+        if not (q[i] == q[i]):
+            continue
+        key = (-q[i], f[i], i)
+        if best is None or key < best:
+            best = key
+    b = -1 if best is None else best[2]
+    return dict(tr, scores=q, best=b, f_best=math.nan if b < 0 else float(f[b]),
+                score=math.nan if b < 0 else float(q[b]), sigma_y=sy)

@@ -54,7 +54,8 @@ struct qmi_ctx {
     // Device buffers, grown on demand.
     enum {
         kT, kY, kE, kCP, kOrder, kRowStart, kK, kR, kRP, kRD, kKS, kCoarse, kCoarse2, kFine, kFine2,
-        kIps, kPeakK, kNpk, kWin, kArgmax, kRes, kFreqs, kProbe, kNumBufs
+        kIps, kPeakK, kNpk, kWin, kArgmax, kRes, kFreqs, kProbe, kTS, kYS, kBandT, kBandCnt,
+        kBandId, kS, kTrials, kTrialK, kNumBufs
     };
     Buf bufs[kNumBufs];
     // Graph cache (device section of one planned group).
@@ -226,12 +227,29 @@ struct CallSpec {
     const qmi_search* search;
     qmi_result* out;
     double* coarse_out;
+    // bands method (search == nullptr, periodogram == false)
+    const qmi_bands* bands;
+    double* trials_out;
+    double* scores_out;
 };
+
+// Per-curve device bytes of the bands method's own buffers (time-ordered copies, band times,
+// spectral windows, trial lists).
+size_t bands_bytes(int64_t n, const qmi_bands& bp) {
+    const int64_t stride = (n + bp.n_bands - 1) / bp.n_bands;
+    size_t b = (size_t)n * 16;
+    b += (size_t)bp.n_keep * (size_t)(stride * 8 + 8);
+    b += (size_t)bp.n_keep * (size_t)bp.n_grid * 8;
+    b += (size_t)bp.n_keep * (size_t)bp.n_trials * 12;
+    return b;
+}
 
 int plan_groups(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, std::vector<Group>& groups) {
     const bool fp64 = cs.kp->precision == QMI_PREC_FP64;
-    const int64_t F1 = cs.periodogram ? cs.n_freq : cs.search->n_coarse;
-    const int64_t F2 = cs.periodogram ? 0 : (int64_t)cs.search->top_k * cs.search->n_fine;
+    const qmi_bands* bp = cs.bands;
+    const int64_t F1 = cs.periodogram ? cs.n_freq
+                       : bp ? (int64_t)bp->n_keep * bp->n_trials : cs.search->n_coarse;
+    const int64_t F2 = (cs.periodogram || bp) ? 0 : (int64_t)cs.search->top_k * cs.search->n_fine;
     const bool two = !cs.periodogram;
     const size_t fixed = 1 << 20;
     if (ctx->budget <= fixed) {
@@ -243,8 +261,9 @@ int plan_groups(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, std::vecto
     size_t used = 0;
     for (int32_t k = 0; k < b->n_curves; ++k) {
         const int64_t n = b->offsets[k + 1] - b->offsets[k];
-        const size_t need = curve_bytes(std::min<int64_t>(n, QMI_MAX_N), F1, F2, fp64,
-                                        cs.ips_out != nullptr, two);
+        const int64_t nn = std::min<int64_t>(n, QMI_MAX_N);
+        const size_t need = curve_bytes(nn, F1, F2, fp64, cs.ips_out != nullptr, two) +
+                            (bp ? bands_bytes(nn, *bp) : 0);
         if (need > avail) {
             set_err(ctx, "curve %d (N=%lld) needs %zu bytes, more than the HBM budget %zu", k,
                     (long long)n, need, ctx->budget);
@@ -321,12 +340,15 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
         return na > nb;
     });
 
-    const int64_t F1 = cs.periodogram ? cs.n_freq : cs.search->n_coarse;
-    const int top_k = cs.periodogram ? 0 : cs.search->top_k;
-    const int n_fine = cs.periodogram ? 0 : cs.search->n_fine;
-    const bool refine = !cs.periodogram && top_k > 0 && n_fine > 0;
+    const qmi_bands* bp = cs.bands;
+    const bool search = !cs.periodogram && !bp;
+    const int64_t F1 = cs.periodogram ? cs.n_freq
+                       : bp ? (int64_t)bp->n_keep * bp->n_trials : cs.search->n_coarse;
+    const int top_k = search ? cs.search->top_k : 0;
+    const int n_fine = search ? cs.search->n_fine : 0;
+    const bool refine = search && top_k > 0 && n_fine > 0;
     const int64_t F2 = refine ? (int64_t)top_k * n_fine : 0;
-    const int score_kind = cs.periodogram ? cs.score : cs.search->score;
+    const int score_kind = cs.periodogram ? cs.score : bp ? bp->score : cs.search->score;
 
     int rc;
 #define ENSURE(id, bytes) \
@@ -350,6 +372,18 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
         ENSURE(qmi_ctx::kFine2, nc * F2 * 8);
     }
     if (cs.ips_out && !cs.dev_outputs) ENSURE(qmi_ctx::kIps, nc * F1 * 24);
+    if (bp) {
+        const int64_t stride = (max_n + bp->n_bands - 1) / bp->n_bands;
+        const int64_t nkt = (int64_t)nc * bp->n_keep;
+        ENSURE(qmi_ctx::kTS, std::max<int64_t>(ns, 1) * 8);
+        ENSURE(qmi_ctx::kYS, std::max<int64_t>(ns, 1) * 8);
+        ENSURE(qmi_ctx::kBandT, nkt * stride * 8);
+        ENSURE(qmi_ctx::kBandCnt, nkt * 4);
+        ENSURE(qmi_ctx::kBandId, nkt * 4);
+        ENSURE(qmi_ctx::kS, nkt * bp->n_grid * 8);
+        ENSURE(qmi_ctx::kTrials, nc * F1 * 8);
+        ENSURE(qmi_ctx::kTrialK, nc * F1 * 4);
+    }
     if (!cs.periodogram) {
         ENSURE(qmi_ctx::kPeakK, nc * std::max(top_k, 1) * sizeof(int32_t));
         ENSURE(qmi_ctx::kNpk, nc * sizeof(int32_t));
@@ -408,6 +442,17 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
                                               : dptr<double>(ctx, qmi_ctx::kIps))
                             : nullptr;
         po.score_kind = score_kind;
+    } else if (bp) {
+        fp.kind = 3;
+        fp.count = (int32_t)F1;
+        fp.stride = (int32_t)F1;
+        fp.list = dptr<double>(ctx, qmi_ctx::kTrials);
+        coarse = dptr<double>(ctx, qmi_ctx::kCoarse);
+        coarse2 = dptr<double>(ctx, qmi_ctx::kCoarse2);
+        po.score = coarse;
+        po.score2 = coarse2;
+        po.ips = nullptr;
+        po.score_kind = score_kind;
     } else {
         const qmi_search* s = cs.search;
         fp.kind = 0;
@@ -440,6 +485,24 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
         }
     }
     DevResult* dres = cs.periodogram ? nullptr : dptr<DevResult>(ctx, qmi_ctx::kRes);
+    BandsDev bd{};
+    if (bp) {
+        bd.f_lo = bp->f_lo;
+        bd.df = (bp->f_hi - bp->f_lo) / (double)(bp->n_grid - 1);
+        bd.n_grid = bp->n_grid;
+        bd.n_bands = bp->n_bands;
+        bd.n_keep = bp->n_keep;
+        bd.n_trials = bp->n_trials;
+        bd.stride = std::max(1, (max_n + bp->n_bands - 1) / bp->n_bands);
+        bd.ts = dptr<double>(ctx, qmi_ctx::kTS);
+        bd.ys = dptr<double>(ctx, qmi_ctx::kYS);
+        bd.band_t = dptr<double>(ctx, qmi_ctx::kBandT);
+        bd.band_cnt = dptr<int32_t>(ctx, qmi_ctx::kBandCnt);
+        bd.band_id = dptr<int32_t>(ctx, qmi_ctx::kBandId);
+        bd.S = dptr<double>(ctx, qmi_ctx::kS);
+        bd.trials = dptr<double>(ctx, qmi_ctx::kTrials);
+        bd.trial_k = dptr<int32_t>(ctx, qmi_ctx::kTrialK);
+    }
 
     // Pair-kernel variant: forced by QMI_OPT_TILE, else the autotuned choice for this length
     // bucket (variant 0 until the bucket has been tuned; see the end of this function).
@@ -476,11 +539,14 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
         HIP_OK(ctx, launch_gram<R>(st, dcp, nc, rows, drow, y, K, rp, rd));
         HIP_OK(ctx, launch_gram_finalize<R>(st, dcp, nc, rd, rp));
         HIP_OK(ctx, launch_ksum<R>(st, dcp, nc, K, ks));
+        if (bp) HIP_OK(ctx, launch_bands(st, dcp, nc, max_n, t, y, bd));
         if (events) pair_event_idx.push_back(ctx->ev_used);
         rec();
         HIP_OK(ctx, launch_pairs<R>(st, dcp, dorder, nc, fp, t, K, rd, rp, ks, po, variant));
         rec();
-        if (!cs.periodogram) {
+        if (bp) {
+            HIP_OK(ctx, launch_bands_best(st, dcp, nc, coarse, coarse2, score_kind, bd, dres));
+        } else if (!cs.periodogram) {
             const qmi_search* s = cs.search;
             HIP_OK(ctx, launch_peaks(st, dcp, nc, coarse, s->n_coarse, fp.f0, fp.df, top_k,
                                      std::max(n_fine, 2), pk));
@@ -511,7 +577,10 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
             u(e), u(dcp),
             u(dorder), u(drow), u(K), u(rp), u(rd), u(ks), u(dfreqs), u(coarse), u(coarse2),
             u(po.ips), u(fine), u(fine2), u(pk.peak_k), u(pk.npk), u(pk.win), u(pk.argmax),
-            u(dres)};
+            u(dres), (uint64_t)(bp != nullptr), dbits(bd.f_lo), dbits(bd.df),
+            (uint64_t)bd.n_grid, (uint64_t)bd.n_bands, (uint64_t)bd.n_keep, (uint64_t)bd.n_trials,
+            (uint64_t)bd.stride, u(bd.ts), u(bd.ys), u(bd.band_t), u(bd.band_cnt), u(bd.band_id),
+            u(bd.S), u(bd.trials), u(bd.trial_k)};
         if (ctx->graph_exec && key == ctx->graph_key) {
             record(ctx);
             HIP_OK(ctx, hipGraphLaunch(ctx->graph_exec, st));
@@ -605,7 +674,26 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
                 HIP_OK(ctx, hipMemcpyAsync(cs.coarse_out + (int64_t)g.c0 * F1, coarse, nc * F1 * 8,
                                            hipMemcpyDeviceToHost, st));
         }
+        if (bp && cs.trials_out)
+            HIP_OK(ctx, hipMemcpyAsync(cs.trials_out + (int64_t)g.c0 * F1, bd.trials,
+                                       nc * F1 * 8, hipMemcpyDeviceToHost, st));
+        if (bp && cs.scores_out)
+            HIP_OK(ctx, hipMemcpyAsync(cs.scores_out + (int64_t)g.c0 * F1, coarse, nc * F1 * 8,
+                                       hipMemcpyDeviceToHost, st));
         HIP_OK(ctx, hipStreamSynchronize(st));
+        if (bp && (cs.trials_out || cs.scores_out)) {
+            // Empty trial slots are never scored: report them as NaN in both outputs.
+            std::vector<double> tr;
+            const double* trp = cs.trials_out ? cs.trials_out + (int64_t)g.c0 * F1 : nullptr;
+            if (!trp) {
+                tr.resize((size_t)nc * F1);
+                HIP_OK(ctx, hipMemcpy(tr.data(), bd.trials, nc * F1 * 8, hipMemcpyDeviceToHost));
+                trp = tr.data();
+            }
+            if (cs.scores_out)
+                for (int64_t q = 0; q < (int64_t)nc * F1; ++q)
+                    if (!(trp[q] == trp[q])) cs.scores_out[(int64_t)g.c0 * F1 + q] = NAN;
+        }
         for (int32_t i = 0; i < nc; ++i) {
             qmi_result& rr = cs.out[g.c0 + i];
             if (cp[i].status != QMI_OK) {
@@ -623,7 +711,8 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
             rr.n = (int32_t)n;
             if (rr.status == QMI_OK)
                 ctx->stats.pair_items += (double)n * (double)(n - 1) / 2.0 *
-                                         (double)(F1 + (int64_t)rr.n_peaks * n_fine);
+                                         (double)(bp ? (int64_t)rr.n_peaks
+                                                     : F1 + (int64_t)rr.n_peaks * n_fine);
         }
     }
     if (cs.periodogram) {
@@ -693,6 +782,22 @@ int run_call(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs) {
                     set_err(ctx, "frequency %d is not finite and >= 0", q);
                     return QMI_EINVAL;
                 }
+    } else if (cs.bands) {
+        const qmi_bands* p = cs.bands;
+        if (!cs.out) { set_err(ctx, "out must not be NULL"); return QMI_EINVAL; }
+        if (!(p->f_lo > 0.0) || !(p->f_hi > p->f_lo) || !std::isfinite(p->f_hi) ||
+            p->n_grid < 2 || p->n_grid > (1 << 24) || p->n_bands < 1 ||
+            p->n_bands > QMI_MAX_BANDS || p->n_keep < 1 || p->n_keep > p->n_bands ||
+            p->n_trials < 1 || p->n_trials > QMI_MAX_TRIALS) {
+            set_err(ctx, "bad bands parameters (f %g..%g, n_grid %d, n_bands %d, n_keep %d, "
+                    "n_trials %d)", p->f_lo, p->f_hi, p->n_grid, p->n_bands, p->n_keep,
+                    p->n_trials);
+            return QMI_EINVAL;
+        }
+        if (p->score != QMI_SCORE_CS_QMI && p->score != QMI_SCORE_NCKP) {
+            set_err(ctx, "unknown score %d", p->score);
+            return QMI_EINVAL;
+        }
     } else {
         const qmi_search* s = cs.search;
         if (!s || !cs.out) { set_err(ctx, "search and out must not be NULL"); return QMI_EINVAL; }
@@ -969,6 +1074,31 @@ int qmi_best_period(qmi_ctx* ctx, const qmi_batch* batch, const qmi_kernel_param
     cs.search = search;
     cs.out = out;
     cs.coarse_out = coarse_out;
+    try {
+        return run_call(ctx, batch, cs);
+    } catch (...) {
+        set_err(ctx, "internal exception");
+        return QMI_EINTERNAL;
+    }
+}
+
+int qmi_bands_best_period(qmi_ctx* ctx, const qmi_batch* batch, const qmi_kernel_params* kp,
+                          const qmi_bands* bands, qmi_result* out, double* trials_out,
+                          double* scores_out) {
+    if (!ctx) return QMI_EINVAL;
+    if (!bands) {
+        set_err(ctx, "bands must not be NULL");
+        return QMI_EINVAL;
+    }
+    CallSpec cs{};
+    cs.dev_inputs = false;
+    cs.dev_outputs = false;
+    cs.periodogram = false;
+    cs.kp = kp;
+    cs.bands = bands;
+    cs.out = out;
+    cs.trials_out = trials_out;
+    cs.scores_out = scores_out;
     try {
         return run_call(ctx, batch, cs);
     } catch (...) {

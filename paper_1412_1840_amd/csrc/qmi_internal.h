@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "qmi.h"
+
 namespace qmi {
 
 // Pair-kernel geometry.  A work item is (curve, tile of kLanes frequency slots); one lane owns one
@@ -61,12 +63,14 @@ constexpr int rows_per_wave() {
 
 // How frequency slot s of curve c maps to a frequency.
 struct FreqPlan {
-    int32_t kind;   // 0 linear grid, 1 explicit list, 2 refinement windows
+    int32_t kind;   // 0 linear grid, 1 explicit list, 2 refinement windows, 3 per-curve lists
     int32_t count;  // slots per curve
     int32_t n_fine;
     int32_t top_k;
+    int32_t stride;  // kind 3: row length of the per-curve lists
+    int32_t pad;
     double f0, df;           // kind 0: f = f0 + s * df
-    const double* list;      // kind 1
+    const double* list;      // kind 1: [count]; kind 3: [curve][stride], NaN = no frequency
     const double* win;       // kind 2: [curve][top_k][2] = (lo, step)
     const int32_t* npk;      // kind 2: [curve] refined peaks
 };
@@ -91,6 +95,28 @@ struct DevResult {
     double f_best, period, score, score_qmi, score_nckp, sigma_y, psnr, coarse_best;
     int32_t coarse_index, peak_rank, fine_index, coarse_argmax, n_peaks, n, status, reserved;
 };
+
+// Bands method (qmi_bands.hip): per-group device buffers and parameters.
+struct BandsDev {
+    double f_lo, df;      // spectral-window grid f_k = f_lo + k df
+    int32_t n_grid, n_bands, n_keep, n_trials;
+    int32_t stride;       // band_t row length (at least the largest band)
+    int32_t pad;
+    double* ts;           // [samples] times in time order (at each curve's offset)
+    double* ys;           // [samples] magnitudes in the same order
+    double* band_t;       // [curve][n_keep][stride] sample times of the kept bands
+    int32_t* band_cnt;    // [curve][n_keep]
+    int32_t* band_id;     // [curve][n_keep] band index of each kept band
+    double* S;            // [curve][n_keep][n_grid] spectral windows
+    double* trials;       // [curve][n_keep * n_trials] trial frequencies, NaN = none
+    int32_t* trial_k;     // [curve][n_keep * n_trials] their grid indices, -1 = none
+};
+size_t bands_prep_lds(int max_n);
+hipError_t launch_bands(hipStream_t st, const CurveParams* cp, int n_curves, int max_n,
+                        const double* t, const double* y, const BandsDev& bd);
+hipError_t launch_bands_best(hipStream_t st, const CurveParams* cp, int n_curves,
+                             const double* score, const double* score2, int score_kind,
+                             const BandsDev& bd, DevResult* res);
 
 // Launchers (qmi_kernels.hip).  All launch on `st` and return hipGetLastError().
 hipError_t launch_prologue(hipStream_t st, CurveParams* cp, int n_curves, int max_n,

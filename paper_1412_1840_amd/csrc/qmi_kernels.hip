@@ -275,6 +275,11 @@ __device__ __forceinline__ double slot_freq(const FreqPlan& fp, int c, int s, bo
     if (!active) return 0.0;
     if (fp.kind == 0) return __dadd_rn(fp.f0, __dmul_rn((double)s, fp.df));
     if (fp.kind == 1) return fp.list[s];
+    if (fp.kind == 3) {
+        const double v = fp.list[(int64_t)c * fp.stride + s];
+        active = v == v;
+        return active ? v : 0.0;
+    }
     const int p = s / fp.n_fine, m = s - p * fp.n_fine;
     if (p >= fp.npk[c]) {
         active = false;
@@ -346,6 +351,11 @@ struct Warp<double, false> {
 };
 
 
+// Adds v to a lane-private LDS accumulator without returning the old value (ds_add_f64).
+__device__ __forceinline__ void ladd(double* p, double v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
 // One term of the pair sums for row i of this wave and the current column j: the kernel value
 // g = exp2(-(d^2 + moff)) with d = h_s(i) h_c(j) - h_c(i) h_s(j) and moff = 0 (or +inf for a row that
 // is masked out, giving g = 0), added to a column partial T, the row sum G and a K-weighted column
@@ -378,7 +388,7 @@ __global__ void __launch_bounds__(kThreads, WPE)
 pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ order,
              FreqPlan fp, const double* __restrict__ t_all, const R* __restrict__ K_all,
              const double* __restrict__ rd_all, const double* __restrict__ rp_all,
-             const R* __restrict__ ks_all, int n_work, PairOut out) {
+             const R* __restrict__ ks_all, int n_work, int xcd_grouped, PairOut out) {
     using W = Warp<R, FOLD32>;
     using V = typename W::V;
     constexpr int ROWS = rows_per_wave<R>();
@@ -386,18 +396,26 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
     constexpr int GRP = 4;  // rows skipped together in the diagonal region
     __shared__ V ph[2][CH][kLanes];
     __shared__ double fq[kWaves][kLanes];  // the lane's frequency, re-read where the warp is formed
+    __shared__ double acc[3][kWaves][kLanes];  // this lane's SJ, ST, SC (added to in place)
 
     const int lane = threadIdx.x & 63;
     const int w = uniform((int)(threadIdx.x >> 6));
     const int tiles = (fp.count + kLanes - 1) / kLanes;
     // The dispatcher deals blocks to the XCDs round robin (block b runs on XCD b mod kXcds), and
-    // each XCD has its own L2.  Give every XCD whole curves (work ranks x, x + kXcds, ...) with
-    // their frequency tiles in consecutive blocks, so that a curve's K table is fetched into one
-    // L2 only.  The grid is padded to a multiple of kXcds curves.
-    const int xcd = (int)(blockIdx.x % kXcds);
-    const int seq = (int)(blockIdx.x / kXcds);
-    const int rank = (seq / tiles) * kXcds + xcd;
-    const int tile = seq - (seq / tiles) * tiles;
+    // each XCD has its own L2.  With enough curves (xcd_grouped), every XCD gets whole curves
+    // (work ranks x, x + kXcds, ...) with their frequency tiles in consecutive blocks, so that a
+    // curve's K table is fetched into one L2 only; the grid is then padded to a multiple of kXcds
+    // curves.  Otherwise consecutive blocks are the tiles of one curve, spread over all XCDs.
+    int rank, tile;
+    if (xcd_grouped) {
+        const int xcd = (int)(blockIdx.x % kXcds);
+        const int seq = (int)(blockIdx.x / kXcds);
+        rank = (seq / tiles) * kXcds + xcd;
+        tile = seq - (seq / tiles) * tiles;
+    } else {
+        rank = (int)(blockIdx.x / tiles);
+        tile = (int)(blockIdx.x - (unsigned)rank * tiles);
+    }
     if (rank >= n_work) return;
     const int c = order[rank];
     const CurveParams P = cp[c];
@@ -426,7 +444,14 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
     const R zero = R(0);
     const R pinf = uniform((R)INFINITY);
 
-    double SJ = 0.0, ST = 0.0, SC = 0.0;  // SC = SCa + SCb
+    // The FP64 sums SJ, ST and SC = SCa + SCb of this lane live in LDS and are added to in place,
+    // so that no registers are held for them across the column loops.
+    double* aSJ = &acc[0][w][lane];
+    double* aST = &acc[1][w][lane];
+    double* aSC = &acc[2][w][lane];
+    *aSJ = 0.0;
+    *aST = 0.0;
+    *aSC = 0.0;
     // Kept in LDS rather than in two registers across the column loops (each wave reads back only
     // what it wrote).
     fq[w][lane] = f;
@@ -483,9 +508,9 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
                     const R Tq = (T4[0] + T4[1]) + (T4[2] + T4[3]);
                     const R Jq = (J4[0] + J4[1]) + (J4[2] + J4[3]);
                     const double Td = (double)Tq;
-                    ST += Td;
-                    SJ += (double)(Jq - ksj);
-                    SC = fma(Td, rj, SC);
+                    ladd(aST, Td);
+                    ladd(aSJ, (double)(Jq - ksj));
+                    ladd(aSC, Td * rj);
                 }
             } else {
                 for (int q = 0; q < jend; ++q) {
@@ -516,36 +541,34 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
                     const R Tq = (T4[0] + T4[1]) + (T4[2] + T4[3]);
                     const R Jq = (J4[0] + J4[1]) + (J4[2] + J4[3]);
                     const double Td = (double)Tq;
-                    ST += Td;
-                    SJ += (double)(Jq - ksb[j]);
-                    SC = fma(Td, rr[j], SC);
+                    ladd(aST, Td);
+                    ladd(aSJ, (double)(Jq - ksb[j]));
+                    ladd(aSC, Td * rr[j]);
                 }
             }
             // Row sums of this chunk, weighted by the FP64 row sums r_i.
             double rk[ROWS];
 #pragma unroll
             for (int m = 0; m < ROWS; ++m) rk[m] = rpb[m];
+            double sca = 0.0;
 #pragma unroll
             for (int m = 0; m < ROWS; ++m) {
-                SC = fma((double)G[m], rk[m], SC);
+                sca = fma((double)G[m], rk[m], sca);
                 G[m] = R(0);
             }
+            ladd(aSC, sca);
             __syncthreads();
         }
     }
 
     // Combine the waves' partial sums in wave order (deterministic), then the epilogue.
-    double* red = reinterpret_cast<double*>(&ph[0][0][0]);
-    red[(w * kLanes + lane) * 3 + 0] = SJ;
-    red[(w * kLanes + lane) * 3 + 1] = ST;
-    red[(w * kLanes + lane) * 3 + 2] = SC;
     __syncthreads();
     if (w != 0 || !active) return;
-    SJ = ST = SC = 0.0;
+    double SJ = 0.0, ST = 0.0, SC = 0.0;
     for (int v = 0; v < kWaves; ++v) {
-        SJ += red[(v * kLanes + lane) * 3 + 0];
-        ST += red[(v * kLanes + lane) * 3 + 1];
-        SC += red[(v * kLanes + lane) * 3 + 2];
+        SJ += acc[0][v][lane];
+        ST += acc[1][v][lane];
+        SC += acc[2][v][lane];
     }
     const int64_t obase = (int64_t)c * fp.count + slot;
     const double N = (double)n;
@@ -804,13 +827,19 @@ int pair_variants() {
 template int pair_variants<float>();
 template int pair_variants<double>();
 
+struct PairGrid {
+    unsigned blocks;
+    int n_work;
+    int xcd_grouped;
+};
+
 template <typename R, int WPE, int CH, bool FOLD32 = false>
 static hipError_t launch_pairs_v(hipStream_t st, const CurveParams* cp, const int32_t* order,
-                                 unsigned grid, const FreqPlan& fp, const double* t, const R* K,
-                                 const double* r, const double* rp, const R* ks,
-                                 int n_work, const PairOut& out) {
-    pairs_kernel<R, WPE, CH, FOLD32><<<grid, kThreads, 0, st>>>(cp, order, fp, t, K, r, rp, ks, n_work,
-                                                        out);
+                                 const PairGrid& g, const FreqPlan& fp, const double* t,
+                                 const R* K, const double* r, const double* rp, const R* ks,
+                                 const PairOut& out) {
+    pairs_kernel<R, WPE, CH, FOLD32><<<g.blocks, kThreads, 0, st>>>(
+        cp, order, fp, t, K, r, rp, ks, g.n_work, g.xcd_grouped, out);
     return hipGetLastError();
 }
 
@@ -820,24 +849,27 @@ hipError_t launch_pairs(hipStream_t st, const CurveParams* cp, const int32_t* or
                         const double* r, const double* rp, const R* ks, const PairOut& out,
                         int variant) {
     if (n_work_curves <= 0 || fp.count <= 0) return hipSuccess;
-    const int tiles = (fp.count + kLanes - 1) / kLanes;
-    const int64_t padded = (int64_t)(n_work_curves + kXcds - 1) / kXcds * kXcds;
-    const unsigned grid = (unsigned)(padded * tiles);
-    const int nw = n_work_curves;
+    const int64_t tiles = (fp.count + kLanes - 1) / kLanes;
+    // Whole curves per XCD once every XCD gets at least 8 of them (enough to balance the XCDs'
+    // loads in the work order); below that, a curve's tiles spread over the whole chip.
+    PairGrid g;
+    g.n_work = n_work_curves;
+    g.xcd_grouped = n_work_curves >= 8 * kXcds;
+    const int64_t rows = g.xcd_grouped ? (int64_t)(n_work_curves + kXcds - 1) / kXcds * kXcds
+                                       : (int64_t)n_work_curves;
+    g.blocks = (unsigned)(rows * tiles);
     if constexpr (sizeof(R) == 4) {
         switch (variant) {
             case kVariantFold32:
-                return launch_pairs_v<R, 2, 64, true>(st, cp, order, grid, fp, t, K, r, rp, ks, nw,
-                                                      out);
-            case 1: return launch_pairs_v<R, 4, 64>(st, cp, order, grid, fp, t, K, r, rp, ks, nw, out);
-            case 2: return launch_pairs_v<R, 2, 32>(st, cp, order, grid, fp, t, K, r, rp, ks, nw, out);
-            case 3: return launch_pairs_v<R, 4, 32>(st, cp, order, grid, fp, t, K, r, rp, ks, nw, out);
-            default: return launch_pairs_v<R, 2, 64>(st, cp, order, grid, fp, t, K, r, rp, ks, nw,
-                                                     out);
+                return launch_pairs_v<R, 2, 64, true>(st, cp, order, g, fp, t, K, r, rp, ks, out);
+            case 1: return launch_pairs_v<R, 4, 64>(st, cp, order, g, fp, t, K, r, rp, ks, out);
+            case 2: return launch_pairs_v<R, 2, 32>(st, cp, order, g, fp, t, K, r, rp, ks, out);
+            case 3: return launch_pairs_v<R, 4, 32>(st, cp, order, g, fp, t, K, r, rp, ks, out);
+            default: return launch_pairs_v<R, 2, 64>(st, cp, order, g, fp, t, K, r, rp, ks, out);
         }
     } else {
         (void)variant;
-        return launch_pairs_v<R, 2, 32>(st, cp, order, grid, fp, t, K, r, rp, ks, nw, out);
+        return launch_pairs_v<R, 2, 32>(st, cp, order, g, fp, t, K, r, rp, ks, out);
     }
 }
 template hipError_t launch_pairs<float>(hipStream_t, const CurveParams*, const int32_t*, int,

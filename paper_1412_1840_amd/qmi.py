@@ -36,11 +36,13 @@ OPT_TILE = 2
 NOT_PERIODIC, PERIODIC, UNDECIDED = 0, 1, 255
 MAX_N = 8192
 MAX_TOPK = 32
+MAX_BANDS = 32
+MAX_TRIALS = 1024
 
 SYMBOLS = ("qmi_create", "qmi_destroy", "qmi_last_error", "qmi_set_option", "qmi_get_stats",
            "qmi_periodogram", "qmi_best_period", "qmi_periodogram_dev", "qmi_best_period_dev",
            "qmi_discriminate", "qmi_calibrate", "qmi_serve_start", "qmi_submit", "qmi_poll",
-           "qmi_serve_stop")
+           "qmi_serve_stop", "qmi_bands_best_period")
 SNR_EDGES = (0.0, 1.5, 2.0, 2.5, 3.5, 5.0, 10.0, 20.0, math.inf)
 
 
@@ -64,6 +66,13 @@ class Search(ctypes.Structure):
     _fields_ = [("f_min", ctypes.c_double), ("f_max", ctypes.c_double),
                 ("n_coarse", ctypes.c_int32), ("top_k", ctypes.c_int32),
                 ("n_fine", ctypes.c_int32), ("score", ctypes.c_int32)]
+
+
+class Bands(ctypes.Structure):
+    _fields_ = [("f_lo", ctypes.c_double), ("f_hi", ctypes.c_double),
+                ("n_grid", ctypes.c_int32), ("n_bands", ctypes.c_int32),
+                ("n_keep", ctypes.c_int32), ("n_trials", ctypes.c_int32),
+                ("score", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Thresholds(ctypes.Structure):
@@ -120,6 +129,8 @@ def lib() -> ctypes.CDLL:
             f = getattr(L, name)
             f.argtypes = [V, P(Batch), P(KernelParams), P(Search), V, V]
             f.restype = ctypes.c_int
+        L.qmi_bands_best_period.argtypes = [V, P(Batch), P(KernelParams), P(Bands), V, V, V]
+        L.qmi_bands_best_period.restype = ctypes.c_int
         L.qmi_discriminate.argtypes = [V, I32, V, P(Thresholds), V]
         L.qmi_discriminate.restype = ctypes.c_int
         L.qmi_calibrate.argtypes = [V, V, V, I32, V, I32, I32, V, V, V, V]
@@ -272,6 +283,27 @@ class Context:
         return res, coarse
 
     # ------------------------------------------------------- device (torch) tensors
+    def bands_best_period(self, offsets, t, y, e, sigma_t: float, n_keep: int = 3,
+                          n_trials: int = 150, n_bands: int = 10, f_lo: float = 0.00125,
+                          f_hi: float = 3.0, n_grid: int = 30000,
+                          sigma_y: float = SIGMA_SILVERMAN, score: int = SCORE_QMI,
+                          precision: int = PREC_MIXED):
+        """Best period over the bands method's trial frequencies: (results, trials, scores),
+        trials and scores of shape [n_curves, n_keep * n_trials] (NaN: empty)."""
+        t, y = _f64(t), _f64(y)
+        e = None if e is None else _f64(e)
+        b, off = self._batch(offsets, t, y, e)
+        res = np.zeros(b.n_curves, RESULT_DTYPE)
+        trials = np.empty((b.n_curves, n_keep * n_trials))
+        scores = np.empty((b.n_curves, n_keep * n_trials))
+        kp = kernel_params(sigma_t, sigma_y, precision)
+        bp = Bands(float(f_lo), float(f_hi), int(n_grid), int(n_bands), int(n_keep),
+                   int(n_trials), int(score), 0)
+        self._check(lib().qmi_bands_best_period(self._h, ctypes.byref(b), ctypes.byref(kp),
+                                                ctypes.byref(bp), res.ctypes.data,
+                                                trials.ctypes.data, scores.ctypes.data))
+        return res, trials, scores
+
     def periodogram_dev(self, offsets, t, y, e, freqs, score_out, sigma_t: float,
                         sigma_y: float = SIGMA_SILVERMAN, score: int = SCORE_QMI,
                         precision: int = PREC_MIXED, ips_out=None):

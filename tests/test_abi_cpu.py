@@ -44,6 +44,8 @@ def test_header_constants_match_binding():
     assert val("QMI_SIGMA_MEDIAN_ERR") == qmi.SIGMA_MEDIAN_ERR
     assert val("QMI_MAX_N") == qmi.MAX_N and val("QMI_MAX_TOPK") == qmi.MAX_TOPK
     assert val("QMI_UNDECIDED") == qmi.UNDECIDED
+    assert val("QMI_MAX_BANDS") == qmi.MAX_BANDS and val("QMI_MAX_TRIALS") == qmi.MAX_TRIALS
+    assert val("QMI_PREC_FOLD32") == qmi.PREC_FOLD32
 
 
 def test_struct_sizes():
@@ -52,6 +54,7 @@ def test_struct_sizes():
     assert ctypes.sizeof(qmi.KernelParams) == 24
     assert ctypes.sizeof(qmi.Search) == 32
     assert ctypes.sizeof(qmi.Thresholds) == 24
+    assert ctypes.sizeof(qmi.Bands) == 40
     assert qmi.RESULT_DTYPE.itemsize == 96
 
 
