@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--tile", type=int, default=0,
                     help="force pair-kernel variant k-1 (0: autotuned)")
     ap.add_argument("--no-graph-check", action="store_true")
+    ap.add_argument("--metric-point-steps", type=int, default=2,
+                    help="timed steps of the same search with every curve at N = 600 (0: skip)")
     ap.add_argument("--bands-steps", type=int, default=2,
                     help="timed calls of the bands-method front end on the same batch (0: skip)")
     return ap.parse_args()
@@ -92,6 +94,7 @@ def serving(qmi, synth, wl, st_, rate, n_req, max_batch, inflight, warmup=0, cur
     th.start()
     got = 0
     deadline = t0 + arrivals[-1] + 120.0 + (n_req / 50.0 if not np.isfinite(rate) else 0.0)
+    next_note = 5000
     while got < n_req and time.perf_counter() < deadline:
         res, tags = ctx.poll(256, 2000)
         now = time.perf_counter()
@@ -99,6 +102,10 @@ def serving(qmi, synth, wl, st_, rate, n_req, max_batch, inflight, warmup=0, cur
             t_done[int(tg)] = now
             status[int(tg)] = r["status"]
         got += len(tags)
+        if got >= next_note:
+            print("serving: %d of %d requests done after %.1f s" % (got, n_req, now - t0),
+                  file=sys.stderr, flush=True)
+            next_note += 5000
     th.join()
     ctx.serve_stop()
     ctx.close()
@@ -125,6 +132,46 @@ def synth_curve(workload, k):
     return {"survey_batch": synth.survey_batch_curve, "long_baseline": synth.long_baseline_curve,
             "serving_stream": synth.serving_curve,
             "survey_stream": synth.survey_stream_curve}[workload](k)
+
+
+def classification_report(qmi, res, truth):
+    """Thresholds per SNR bin calibrated (F1-maximising sweep, Sec. 4.1) on the curves with
+    k mod 4 in {0, 1}, evaluated on the others: per bin and overall precision, recall, F1 and hit
+    rate (periodic, classified periodic and period recovered within 1 / (2T), over all periodic
+    curves; Sec. 3.2)."""
+    nc = len(truth)
+    is_per = np.array([c.periodic for c in truth])
+    rec = np.array([bool(c.periodic) and abs(res["f_best"][k] - 1.0 / c.period)
+                    <= 0.5 / float(c.t.max() - c.t.min()) for k, c in enumerate(truth)])
+    train = np.array([k % 4 < 2 for k in range(nc)])
+    cal = qmi.calibrate(res["score_qmi"][train], res["psnr"][train], is_per[train])
+    th = [float(x) if np.isfinite(x) else 1e300 for x in cal["th"]]
+    dec = qmi.discriminate(res, qmi.SNR_EDGES, th) == qmi.PERIODIC
+    test = ~train
+
+    def quality(sel):
+        tp = int(np.sum(dec & is_per & sel))
+        fp = int(np.sum(dec & ~is_per & sel))
+        fn = int(np.sum(~dec & is_per & sel))
+        tps = int(np.sum(dec & rec & sel))
+        n_per = int(np.sum(is_per & sel))
+        p = tp / (tp + fp) if tp + fp else None
+        r = tp / (tp + fn) if tp + fn else None
+        f1 = (2 * p * r / (p + r)) if p and r else None
+        return {"curves": int(np.sum(sel)), "periodic": n_per, "precision": p, "recall": r,
+                "f1": f1, "hit_rate": tps / n_per if n_per else None}
+
+    edges = list(qmi.SNR_EDGES)
+    bins = np.array([np.searchsorted(edges, v, side="right") - 1 if np.isfinite(v) else -1
+                     for v in res["psnr"]])
+    per_bin = []
+    for b in range(len(edges) - 1):
+        q = quality(test & (bins == b))
+        q["bin"] = [edges[b], edges[b + 1] if np.isfinite(edges[b + 1]) else None]
+        q["threshold"] = th[b] if th[b] < 1e300 else None
+        per_bin.append(q)
+    return {"score": "qmi", "calibrated_on": "k mod 4 in {0,1}", "evaluated_on": "k mod 4 in {2,3}",
+            "overall": quality(test), "per_snr_bin": per_bin}
 
 
 def measured_traffic(workload, n_curves, variant):
@@ -266,12 +313,44 @@ def main():
                                        [O.silverman_sigma(c.y) for c in cs], [fr] * len(cs), 1)
         cdt = time.perf_counter() - c0
         citems = sum(c.n * (c.n - 1) / 2.0 * len(fr) for c in cs)
+        # The same oracle on one thread (first curve, 64 of the frequencies).
+        f1 = fr[:64]
+        c1 = time.perf_counter()
+        O.batch_information_potentials([cs[0].t], [cs[0].y], [st_], [O.silverman_sigma(cs[0].y)],
+                                       [f1], 1, 1)
+        c1dt = time.perf_counter() - c1
+        items1 = cs[0].n * (cs[0].n - 1) / 2.0 * len(f1)
         cpu = {"value": (citems / cdt) / items_per_curve, "unit": "lightcurves/s",
                "cores": threads, "kind": "oracle",
+               "single_thread_value": (items1 / c1dt) / items_per_curve,
+               "single_thread_items_per_s": items1 / c1dt,
                "sample": "FP64 oracle pair sums of %d curves x %d coarse frequencies (%.3g pair*f "
                          "items in %.1f s = %.3g items/s), scaled by the %.3g items one curve of "
                          "the workload needs" % (len(cs), len(fr), citems, cdt, citems / cdt,
                                                  items_per_curve)}
+
+    # The metric's own point: every curve of the batch generator at N = 600, 20 000 coarse
+    # frequencies plus the refinement, timed like the main steps.
+    metric_point = None
+    if a.metric_point_steps > 0 and a.workload == "survey_batch":
+        mb = synth.make_batch(a.workload, range(a.n_curves), n=600)
+        MT = torch.from_numpy(mb.t).to(dev)
+        MY = torch.from_numpy(mb.y).to(dev)
+        ME = torch.from_numpy(mb.e).to(dev)
+        ctx.best_period_dev(mb.offsets, MT, MY, ME, st_, **kw)
+        torch.cuda.synchronize()
+        m0 = time.perf_counter()
+        mitems = 0.0
+        for _ in range(a.metric_point_steps):
+            ctx.best_period_dev(mb.offsets, MT, MY, ME, st_, **kw)
+            mitems += ctx.stats()["pair_items"]
+        torch.cuda.synchronize()
+        mdt = time.perf_counter() - m0
+        metric_point = {"n": 600, "n_curves": mb.n_curves,
+                        "value": mb.n_curves * a.metric_point_steps / mdt,
+                        "unit": "lightcurves/s", "gpairs_per_s": mitems / mdt / 1e9,
+                        "roofline_frac_wall": mitems / mdt / PEAK_ITEMS_PER_S}
+        del MT, MY, ME
 
     # Bands-method front end (Sec. 3.1: 3 bands x 150 trial frequencies instead of the coarse
     # grid and refinement) on the same batch, and the period recovery of both front ends against
@@ -315,6 +394,12 @@ def main():
                  / max(len(in_range), 1),
                  "recovered_coarse_to_fine_in_range": sum(recovered(res, k) for k in in_range)
                  / max(len(in_range), 1)}
+
+    # Classification quality of the discriminator (Sec. 4.1) against the generator's truth.
+    classification = None
+    if a.workload in ("survey_batch", "long_baseline", "serving_stream", "survey_stream"):
+        classification = classification_report(
+            qmi, res, [synth_curve(a.workload, k) for k in range(nc)])
 
     serve = None
     sweep = None
@@ -369,6 +454,8 @@ def main():
                      "probe_fma_per_s": probe and probe.get("fma_per_s")},
         "graph": graph,
         "bands": bands,
+        "metric_point": metric_point,
+        "classification": classification,
         "plain": plain,
         "serving": serve,
         "serving_sweep": sweep,

@@ -235,10 +235,11 @@ gram_finalize_kernel(CurveParams* __restrict__ cp, const double* __restrict__ rd
 }
 
 // Column K-sums in the pair kernel's own rounding order: for pass p, wave w and column j, the
-// sum over the wave's rows i < j of K(i, j), accumulated in the kernel type row by row exactly as
-// the pair kernel accumulates K(i, j) g_ij.  Where every g_ij of a column is exactly 1 (coincident
-// phases, f = 0) the kernel's column sum equals this value bit for bit, so their difference is
-// exactly zero.  One block per curve.
+// sum over the wave's rows i < j of K(i, j), accumulated in the kernel type exactly as the pair
+// kernel accumulates K(i, j) g_ij: four interleaved partials (rows m mod 4, each row by row with
+// an fma), combined as (a0 + a1) + (a2 + a3).  Where every g_ij of a column is exactly 1
+// (coincident phases, f = 0) the kernel's column sum equals this value bit for bit, so their
+// difference is exactly zero.  One block per curve.
 constexpr int kKsBlock = 256;
 
 template <typename R>
@@ -260,9 +261,9 @@ ksum_kernel(const CurveParams* __restrict__ cp, const R* __restrict__ K, R* __re
         int cnt = (j - base - w + kWaves - 1) / kWaves;
         cnt = cnt < 0 ? 0 : (cnt > nrows ? nrows : cnt);
         const R* kr = K + P.koff + (int64_t)j * P.npad + kperm(base + w);
-        R acc = R(0);
-        for (int m = 0; m < cnt; ++m) acc = fma(kr[m], R(1), acc);
-        ks[P.ksoff + e] = acc;
+        R acc[4] = {R(0), R(0), R(0), R(0)};
+        for (int m = 0; m < cnt; ++m) acc[m & 3] = fma(kr[m], R(1), acc[m & 3]);
+        ks[P.ksoff + e] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     }
 }
 

@@ -102,6 +102,9 @@ class SurveyRunner:
         from . import qmi
         if self._ctx is None:
             self._ctx = qmi.Context(self.device)
+            # Batches differ in composition, so a captured graph would never be replayed; eager
+            # launches also let the library time the pair kernels.
+            self._ctx.set_option(qmi.OPT_USE_GRAPH, 0)
         s = self.search
         res, _ = self._ctx.best_period(batch.offsets, batch.t, batch.y, batch.e, self.sigma_t,
                                        f_min=s["f_min"], f_max=s["f_max"],

@@ -1,7 +1,8 @@
 """Writes <workload>_oracle.json: the FP64 oracle's full coarse-to-fine search of the first curves
 of a workload (survey_batch: 20 000 coarse + 10 x 1000 refined frequencies on [1e-3, 10] 1/d;
-long_baseline: the same on [1e-3, 20] 1/d over a 7000-day baseline; sigma_t = 0.3, Silverman
-sigma_y), for the GPU parity tests of the best period at full size.
+long_baseline: the same on [1e-3, 20] 1/d over a 7000-day baseline; survey_stream: 30 000 coarse +
+10 x 1000 refined on [1e-3, 10] 1/d; sigma_t = 0.3, Silverman sigma_y), for the GPU parity tests
+of the best period at full size.
 
     python tests/golden/make_survey_parity.py [n_curves] [threads] [workload]
 
@@ -27,7 +28,8 @@ def main():
     threads = int(sys.argv[2]) if len(sys.argv) > 2 else 0
     workload = sys.argv[3] if len(sys.argv) > 3 else "survey_batch"
     wl = synth.WORKLOADS[workload]
-    make = {"survey_batch": synth.survey_batch_curve, "long_baseline": synth.long_baseline_curve}[workload]
+    make = {"survey_batch": synth.survey_batch_curve, "long_baseline": synth.long_baseline_curve,
+            "survey_stream": synth.survey_stream_curve}[workload]
     kw = dict(f_min=wl["f_min"], f_max=wl["f_max"], n_coarse=wl["n_coarse"], top_k=wl["top_k"],
               n_fine=wl["n_fine"])
     out_path = os.path.join(HERE, "%s_oracle.json" % workload)

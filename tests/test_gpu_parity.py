@@ -67,6 +67,9 @@ def test_periodogram_ragged_sizes(ctx):
         np.testing.assert_allclose(ips[k, :, 1], ref.ipt, rtol=V_RTOL)
         np.testing.assert_allclose(ips[k, :, 2], ref.vc, rtol=V_RTOL)
         assert floor_rel(sc[k], O.qmi(ref)).max() <= QMI_TOL, c.n
+        # f = 0: every kernel value is exactly 1, every FP32 partial sum is exact (integers, or
+        # bit-identical to the precomputed K sums), so QMI(0) = 0 up to FP64 rounding.
+        assert abs(sc[k, 0]) <= 1e-12, (c.n, sc[k, 0])
     print("worst QMI rel err %.3g" % worst)
 
 
@@ -395,23 +398,28 @@ def test_autotune_on_batch_larger_than_probe(ctx):
         assert floor_rel(c_t2[k], c_f[k]).max() <= QMI_TOL
 
 
-def test_survey_batch_best_period_matches_oracle_full_search():
-    """Full-size search (20 000 coarse + 10 x 1000 refined frequencies) of the first 64 curves of
-    the survey batch against the stored FP64 oracle results (tests/golden/make_survey_parity.py).
-    Indices must agree; where the oracle's best and runner-up refined scores are within 1e-5 of
-    each other (a flat maximum: several grid points are correct), the GPU's choice must score
-    within that margin of the best under the oracle."""
+def _golden_search(workload, make):
+    """GPU full-size search of the stored curves of a workload: (records, curves, results)."""
     import json
     import os
 
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
-                        "survey_batch_oracle.json")
+                        "%s_oracle.json" % workload)
+    if not os.path.exists(path):
+        pytest.skip("no stored oracle search for %s" % workload)
     gold = json.load(open(path))
     recs = gold["curves"]
-    curves = [synth.survey_batch_curve(r["k"]) for r in recs]
+    curves = [make(r["k"]) for r in recs]
     b = pack(curves)
     with qmi.Context(0) as c2:
         res, _ = c2.best_period(b.offsets, b.t, b.y, b.e, gold["sigma_t"], **gold["search"])
+    return gold, recs, curves, res
+
+
+def _compare_best(gold, recs, curves, res, name):
+    """Indices must agree; where the oracle's best and runner-up refined scores are within 1e-5
+    of each other (a flat maximum: several grid points are correct), the GPU's choice must score
+    within that margin of the best under the oracle."""
     exact, ties, bad = 0, [], []
     for r, c, g in zip(res, curves, recs):
         assert r["status"] == 0 and r["n_peaks"] == g["n_peaks"]
@@ -430,10 +438,25 @@ def test_survey_batch_best_period_matches_oracle_full_search():
         else:
             bad.append((g["k"], dict(coarse=(g["coarse_index"], int(r["coarse_index"])),
                                      fine=(g["fine_index"], int(r["fine_index"])))))
-    print("survey batch: %d of %d identical, %d flat-maximum ties %s" % (exact, len(recs),
-                                                                         len(ties), ties))
+    print("%s: %d of %d identical, %d flat-maximum ties %s" % (name, exact, len(recs), len(ties),
+                                                               ties))
     assert not bad, bad
     assert exact + len(ties) == len(recs)
+
+
+def test_survey_stream_best_period_matches_oracle_full_search():
+    """The survey-stream workload's search (30 000 coarse + 10 x 1000 refined frequencies, N
+    lognormal in [100, 1500]) against the stored FP64 oracle search of its first curves."""
+    gold, recs, curves, res = _golden_search("survey_stream", synth.survey_stream_curve)
+    _compare_best(gold, recs, curves, res, "survey stream")
+
+
+def test_survey_batch_best_period_matches_oracle_full_search():
+    """Full-size search (20 000 coarse + 10 x 1000 refined frequencies) of the stored curves of
+    the survey batch against the FP64 oracle results (tests/golden/make_survey_parity.py), then
+    the discriminator's decisions."""
+    gold, recs, curves, res = _golden_search("survey_batch", synth.survey_batch_curve)
+    _compare_best(gold, recs, curves, res, "survey batch")
     # Discriminator: thresholds calibrated by the oracle on its own scores, then the decision of
     # every curve from the GPU result (score at f_best, pSNR) against the oracle's decision.
     psn = [O.psnr(c.y, c.e) for c in curves]
