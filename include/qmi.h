@@ -261,6 +261,44 @@ int qmi_bands_best_period(qmi_ctx *ctx, const qmi_batch *batch, const qmi_kernel
                           double *scores_out);
 
 /*
+ * Preprocessing of Sec. 5.2, per curve: with error_cut, samples with e_i >= mean(e) + 3 sd(e) are
+ * removed (sd with N - 1; when all error bars are equal nothing is removed); a curve left with
+ * fewer than min_samples samples is rejected (the paper: 50); with detrend, the chi^2 line
+ * a0 + a1 t minimising sum (a0 + a1 t_i - y_i)^2 / e_i^2 is subtracted from y when the Pearson
+ * correlation between the line and the magnitudes exceeds 0.5.  error_cut and detrend need error
+ * bars (detrend needs e > 0; a curve with e <= 0 is rejected).
+ */
+typedef struct {
+    int32_t error_cut;
+    int32_t min_samples; /* 2 .. QMI_MAX_N */
+    int32_t detrend;
+    int32_t reserved;
+} qmi_preprocess_params;
+
+/*
+ * Preprocess a host batch.  Outputs (host, caller-owned) form a new batch: offsets_out
+ * [n_curves + 1], t_out / y_out / e_out with room for the input's total sample count (e_out may
+ * be NULL only when the batch has no error bars).  A rejected curve (invalid input, too short
+ * after the cut) keeps no samples and gets status QMI_EINVAL in status_out (nullable,
+ * [n_curves]); detrended_out (nullable, [n_curves]) is 1 where the line was subtracted.  The kept
+ * samples stay in input order.
+ */
+int qmi_preprocess(qmi_ctx *ctx, const qmi_batch *batch, const qmi_preprocess_params *params,
+                   int64_t *offsets_out, double *t_out, double *y_out, double *e_out,
+                   int32_t *status_out, uint8_t *detrended_out);
+
+/*
+ * Whitening for the search of further modes (Sec. 7.1): per curve, fold with periods[k] (phase
+ * t/P - floor(t/P)), order the samples by phase (stable), take as template at folded position i
+ * the mean of the w = min(window, N) samples at positions i - w/2 .. i - w/2 + w - 1 (cyclic),
+ * and write y - template to y_out (host, [total samples], input order).  The paper uses window 30.
+ * A curve with invalid input or a period that is not finite and > 0 gets status QMI_EINVAL
+ * (status_out nullable) and NaN outputs.
+ */
+int qmi_whiten(qmi_ctx *ctx, const qmi_batch *batch, const double *periods, int32_t window,
+               double *y_out, int32_t *status_out);
+
+/*
  * Periodic / non-periodic decision (Sec. 4.1): for curve k with status QMI_OK, pSNR p (psnr[k] if
  * psnr is not NULL, else best[k].psnr) in bin b and score s = best[k].score_qmi or score_nckp as
  * th->score selects, is_periodic[k] = QMI_PERIODIC iff s > th->th[b] (strict).  Curves with a bad

@@ -486,3 +486,98 @@ def bands_best_period(t, y, e, sigma_t: float, sigma_y_rule: float, n_keep: int 
     b = -1 if best is None else best[2]
     return dict(tr, scores=q, best=b, f_best=math.nan if b < 0 else float(f[b]),
                 score=math.nan if b < 0 else float(q[b]), sigma_y=sy)
+
+
+# ------------------------------------------------------------------------------------------
+# Preprocessing (Sec. 5.2) and whitening for multimode search (Sec. 7.1)
+# ------------------------------------------------------------------------------------------
+# Readings: the error-bar statistics are the mean and the standard deviation with N - 1; a sample
+# is kept iff e_i < mean + 3 std, except that when all error bars are equal nothing is an outlier
+# and every sample is kept; a curve left with fewer than min_samples samples is rejected.  The
+# chi^2 line minimises sum (a0 + a1 t_i - y_i)^2 / e_i^2; it is subtracted (a0 + a1 t) when the
+# Pearson correlation between the magnitudes and the fitted line exceeds 0.5.  Whitening folds
+# with the period P0 (phase t/P0 - floor(t/P0)), orders the samples by phase (stable), takes as
+# template at folded position i the mean of the w = min(30, N) samples at positions i - w//2 ..
+# i - w//2 + w - 1 (cyclically: the folded curve is periodic), subtracts it, and returns the
+# samples in their input order.
+
+def error_bar_cut(e, k_sigma: float = 3.0) -> np.ndarray:
+    """Boolean mask of the samples kept by the error-bar cut (Sec. 5.2)."""
+    e = np.asarray(e, np.float64)
+    n = len(e)
+    if n == 0 or all(v == e[0] for v in e):
+        return np.ones(n, bool)
+    mean = 0.0
+    for v in e:
+        mean += v
+    mean /= n
+    ss = 0.0
+    for v in e:
+        ss += (v - mean) * (v - mean)
+    sd = math.sqrt(ss / (n - 1)) if n > 1 else 0.0
+    thr = mean + k_sigma * sd
+    return np.array([v < thr for v in e])
+
+
+def chi2_line(t, y, e) -> Tuple[float, float]:
+    """(a0, a1) minimising sum (a0 + a1 t_i - y_i)^2 / e_i^2, from the normal equations."""
+    S = Sx = Sy = Sxx = Sxy = 0.0
+    for ti, yi, ei in zip(t, y, e):
+        w = 1.0 / (ei * ei)
+        S += w
+        Sx += w * ti
+        Sy += w * yi
+        Sxx += w * ti * ti
+        Sxy += w * ti * yi
+    den = S * Sxx - Sx * Sx
+    a1 = (S * Sxy - Sx * Sy) / den if den != 0.0 else 0.0
+    a0 = (Sy - a1 * Sx) / S
+    return a0, a1
+
+
+def pearson(x, y) -> float:
+    n = len(x)
+    mx = sum(x) / n
+    my = sum(y) / n
+    sxy = sum((a - mx) * (b - my) for a, b in zip(x, y))
+    sxx = sum((a - mx) * (a - mx) for a in x)
+    syy = sum((b - my) * (b - my) for b in y)
+    return sxy / math.sqrt(sxx * syy) if sxx > 0.0 and syy > 0.0 else 0.0
+
+
+def preprocess(t, y, e, min_samples: int = 50, min_corr: float = 0.5) -> Dict[str, object]:
+    """Error-bar cut, minimum length, then the chi^2 linear detrending (Sec. 5.2)."""
+    t = np.asarray(t, np.float64)
+    y = np.asarray(y, np.float64)
+    e = np.asarray(e, np.float64)
+    keep = error_bar_cut(e)
+    t, y, e = t[keep], y[keep], e[keep]
+    if len(t) < min_samples:
+        return {"t": t, "y": y, "e": e, "ok": False, "detrended": False, "line": (0.0, 0.0)}
+    a0, a1 = chi2_line(t, y, e)
+    fit = a0 + a1 * t
+    r = pearson(fit, y)
+    detrended = r > min_corr
+    if detrended:
+        y = y - fit
+    return {"t": t, "y": y, "e": e, "ok": True, "detrended": bool(detrended), "line": (a0, a1),
+            "corr": r}
+
+
+def whiten(t, y, period: float, window: int = 30) -> np.ndarray:
+    """The curve minus its folded moving-average template (Sec. 7.1), in input order."""
+    t = np.asarray(t, np.float64)
+    y = np.asarray(y, np.float64)
+    n = len(t)
+    x = t / period
+    phase = x - np.floor(x)
+    order = np.argsort(phase, kind="stable")
+    ys = y[order]
+    w = min(window, n)
+    out = np.empty(n)
+    for i in range(n):
+        s = 0.0
+        for m in range(w):
+            s += ys[(i - w // 2 + m) % n]
+        out[order[i]] = ys[i] - s / w
+    return out

@@ -55,7 +55,8 @@ struct qmi_ctx {
     enum {
         kT, kY, kE, kCP, kOrder, kRowStart, kK, kR, kRP, kRD, kKS, kCoarse, kCoarse2, kFine, kFine2,
         kIps, kPeakK, kNpk, kWin, kArgmax, kRes, kFreqs, kProbe, kTS, kYS, kBandT, kBandCnt,
-        kBandId, kS, kTrials, kTrialK, kNumBufs
+        kBandId, kS, kTrials, kTrialK, kPOff, kPStIn, kPCnt, kPSt, kPDet, kPTo, kPYo, kPEo,
+        kPPer, kNumBufs
     };
     Buf bufs[kNumBufs];
     // Graph cache (device section of one planned group).
@@ -167,7 +168,7 @@ int check_batch(qmi_ctx* ctx, const qmi_batch* b, bool need_e) {
             return QMI_EINVAL;
         }
     if (need_e && !b->e) {
-        set_err(ctx, "QMI_SIGMA_MEDIAN_ERR needs error bars (batch e is NULL)");
+        set_err(ctx, "this call needs error bars (batch e is NULL)");
         return QMI_EINVAL;
     }
     return QMI_OK;
@@ -1101,6 +1102,187 @@ int qmi_bands_best_period(qmi_ctx* ctx, const qmi_batch* batch, const qmi_kernel
     cs.scores_out = scores_out;
     try {
         return run_call(ctx, batch, cs);
+    } catch (...) {
+        set_err(ctx, "internal exception");
+        return QMI_EINTERNAL;
+    }
+}
+
+namespace {
+
+// Uploads a host batch (arrays, offsets) and the per-curve host statuses; returns max N of the
+// valid curves through *max_n.
+int upload_batch(qmi_ctx* ctx, const qmi_batch* b, const std::vector<int32_t>& status,
+                 int* max_n) {
+    const int32_t nc = b->n_curves;
+    const int64_t ns = b->offsets[nc];
+    int rc;
+    if ((rc = ensure(ctx, qmi_ctx::kT, std::max<int64_t>(ns, 1) * 8)) != QMI_OK) return rc;
+    if ((rc = ensure(ctx, qmi_ctx::kY, std::max<int64_t>(ns, 1) * 8)) != QMI_OK) return rc;
+    if (b->e && (rc = ensure(ctx, qmi_ctx::kE, std::max<int64_t>(ns, 1) * 8)) != QMI_OK) return rc;
+    if ((rc = ensure(ctx, qmi_ctx::kPOff, (nc + 1) * 8)) != QMI_OK) return rc;
+    if ((rc = ensure(ctx, qmi_ctx::kPStIn, nc * 4)) != QMI_OK) return rc;
+    hipStream_t st = ctx->stream;
+    HIP_OK(ctx, hipMemcpyAsync(dptr<double>(ctx, qmi_ctx::kT), b->t, ns * 8,
+                               hipMemcpyHostToDevice, st));
+    HIP_OK(ctx, hipMemcpyAsync(dptr<double>(ctx, qmi_ctx::kY), b->y, ns * 8,
+                               hipMemcpyHostToDevice, st));
+    if (b->e)
+        HIP_OK(ctx, hipMemcpyAsync(dptr<double>(ctx, qmi_ctx::kE), b->e, ns * 8,
+                                   hipMemcpyHostToDevice, st));
+    HIP_OK(ctx, hipMemcpyAsync(dptr<int64_t>(ctx, qmi_ctx::kPOff), b->offsets, (nc + 1) * 8,
+                               hipMemcpyHostToDevice, st));
+    HIP_OK(ctx, hipMemcpyAsync(dptr<int32_t>(ctx, qmi_ctx::kPStIn), status.data(), nc * 4,
+                               hipMemcpyHostToDevice, st));
+    int mx = 1;
+    for (int32_t k = 0; k < nc; ++k)
+        if (status[k] == QMI_OK)
+            mx = std::max<int>(mx, (int)(b->offsets[k + 1] - b->offsets[k]));
+    *max_n = mx;
+    return QMI_OK;
+}
+
+int preprocess_call(qmi_ctx* ctx, const qmi_batch* b, const qmi_preprocess_params* pp,
+                    int64_t* offsets_out, double* t_out, double* y_out, double* e_out,
+                    int32_t* status_out, uint8_t* detrended_out) {
+    std::lock_guard<std::mutex> lk(ctx->call_mu);
+    ctx->err.clear();
+    if (!pp || !offsets_out || !t_out || !y_out) {
+        set_err(ctx, "params, offsets_out, t_out and y_out must not be NULL");
+        return QMI_EINVAL;
+    }
+    int rc = check_batch(ctx, b, pp->error_cut || pp->detrend);
+    if (rc) return rc;
+    if (b->e && !e_out) {
+        set_err(ctx, "e_out must not be NULL when the batch has error bars");
+        return QMI_EINVAL;
+    }
+    if (pp->min_samples < 2 || pp->min_samples > QMI_MAX_N) {
+        set_err(ctx, "min_samples must be in [2, %d] (got %d)", QMI_MAX_N, pp->min_samples);
+        return QMI_EINVAL;
+    }
+    const int32_t nc = b->n_curves;
+    offsets_out[0] = 0;
+    if (nc == 0) return QMI_OK;
+    const int64_t ns = b->offsets[nc];
+    std::vector<int32_t> st_in(nc);
+    for (int32_t k = 0; k < nc; ++k) {
+        st_in[k] = host_curve_status(b, k, true);
+        if (st_in[k] == QMI_OK && pp->detrend)
+            for (int64_t i = b->offsets[k]; i < b->offsets[k + 1]; ++i)
+                if (!(b->e[i] > 0.0)) st_in[k] = QMI_EINVAL;  // chi^2 weights need e > 0
+    }
+    HIP_OK(ctx, hipSetDevice(ctx->device));
+    int max_n = 0;
+    if ((rc = upload_batch(ctx, b, st_in, &max_n)) != QMI_OK) return rc;
+    const int ids[] = {qmi_ctx::kPTo, qmi_ctx::kPYo, qmi_ctx::kPEo};
+    for (int id : ids)
+        if ((rc = ensure(ctx, id, std::max<int64_t>(ns, 1) * 8)) != QMI_OK) return rc;
+    if ((rc = ensure(ctx, qmi_ctx::kPCnt, nc * 4)) != QMI_OK) return rc;
+    if ((rc = ensure(ctx, qmi_ctx::kPSt, nc * 4)) != QMI_OK) return rc;
+    if ((rc = ensure(ctx, qmi_ctx::kPDet, nc)) != QMI_OK) return rc;
+    PrepDev pd{};
+    pd.error_cut = pp->error_cut ? 1 : 0;
+    pd.detrend = pp->detrend ? 1 : 0;
+    pd.min_samples = pp->min_samples;
+    pd.status_in = dptr<int32_t>(ctx, qmi_ctx::kPStIn);
+    pd.counts = dptr<int32_t>(ctx, qmi_ctx::kPCnt);
+    pd.status = dptr<int32_t>(ctx, qmi_ctx::kPSt);
+    pd.detrended = dptr<uint8_t>(ctx, qmi_ctx::kPDet);
+    pd.t_out = dptr<double>(ctx, qmi_ctx::kPTo);
+    pd.y_out = dptr<double>(ctx, qmi_ctx::kPYo);
+    pd.e_out = dptr<double>(ctx, qmi_ctx::kPEo);
+    hipStream_t st = ctx->stream;
+    HIP_OK(ctx, launch_prep(st, nc, dptr<int64_t>(ctx, qmi_ctx::kPOff),
+                            dptr<double>(ctx, qmi_ctx::kT), dptr<double>(ctx, qmi_ctx::kY),
+                            b->e ? dptr<double>(ctx, qmi_ctx::kE) : nullptr, pd));
+    std::vector<int32_t> cnt(nc), stt(nc);
+    std::vector<uint8_t> det(nc);
+    std::vector<double> ht(ns), hy(ns), he(b->e ? ns : 0);
+    HIP_OK(ctx, hipMemcpyAsync(cnt.data(), pd.counts, nc * 4, hipMemcpyDeviceToHost, st));
+    HIP_OK(ctx, hipMemcpyAsync(stt.data(), pd.status, nc * 4, hipMemcpyDeviceToHost, st));
+    HIP_OK(ctx, hipMemcpyAsync(det.data(), pd.detrended, nc, hipMemcpyDeviceToHost, st));
+    HIP_OK(ctx, hipMemcpyAsync(ht.data(), pd.t_out, ns * 8, hipMemcpyDeviceToHost, st));
+    HIP_OK(ctx, hipMemcpyAsync(hy.data(), pd.y_out, ns * 8, hipMemcpyDeviceToHost, st));
+    if (b->e)
+        HIP_OK(ctx, hipMemcpyAsync(he.data(), pd.e_out, ns * 8, hipMemcpyDeviceToHost, st));
+    HIP_OK(ctx, hipStreamSynchronize(st));
+    // Dense output: each accepted curve's kept samples; rejected curves keep none.
+    int64_t o = 0;
+    for (int32_t k = 0; k < nc; ++k) {
+        const int64_t a = b->offsets[k];
+        const int64_t m = stt[k] == QMI_OK ? cnt[k] : 0;
+        std::memcpy(t_out + o, ht.data() + a, m * 8);
+        std::memcpy(y_out + o, hy.data() + a, m * 8);
+        if (b->e) std::memcpy(e_out + o, he.data() + a, m * 8);
+        o += m;
+        offsets_out[k + 1] = o;
+        if (status_out) status_out[k] = stt[k];
+        if (detrended_out) detrended_out[k] = det[k];
+    }
+    return QMI_OK;
+}
+
+int whiten_call(qmi_ctx* ctx, const qmi_batch* b, const double* periods, int32_t window,
+                double* y_out, int32_t* status_out) {
+    std::lock_guard<std::mutex> lk(ctx->call_mu);
+    ctx->err.clear();
+    int rc = check_batch(ctx, b, false);
+    if (rc) return rc;
+    if (!periods || !y_out || window < 1) {
+        set_err(ctx, "periods and y_out must not be NULL and window must be >= 1");
+        return QMI_EINVAL;
+    }
+    const int32_t nc = b->n_curves;
+    if (nc == 0) return QMI_OK;
+    const int64_t ns = b->offsets[nc];
+    std::vector<int32_t> st_in(nc);
+    for (int32_t k = 0; k < nc; ++k) {
+        st_in[k] = host_curve_status(b, k, true);
+        if (!(periods[k] > 0.0) || !std::isfinite(periods[k])) st_in[k] = QMI_EINVAL;
+    }
+    HIP_OK(ctx, hipSetDevice(ctx->device));
+    int max_n = 0;
+    if ((rc = upload_batch(ctx, b, st_in, &max_n)) != QMI_OK) return rc;
+    if ((rc = ensure(ctx, qmi_ctx::kPYo, std::max<int64_t>(ns, 1) * 8)) != QMI_OK) return rc;
+    if ((rc = ensure(ctx, qmi_ctx::kPPer, nc * 8)) != QMI_OK) return rc;
+    hipStream_t st = ctx->stream;
+    double* dper = dptr<double>(ctx, qmi_ctx::kPPer);
+    double* dy = dptr<double>(ctx, qmi_ctx::kPYo);
+    HIP_OK(ctx, hipMemcpyAsync(dper, periods, nc * 8, hipMemcpyHostToDevice, st));
+    HIP_OK(ctx, launch_whiten(st, nc, max_n, dptr<int64_t>(ctx, qmi_ctx::kPOff),
+                              dptr<double>(ctx, qmi_ctx::kT), dptr<double>(ctx, qmi_ctx::kY), dper,
+                              window, dptr<int32_t>(ctx, qmi_ctx::kPStIn), dy));
+    HIP_OK(ctx, hipMemcpyAsync(y_out, dy, ns * 8, hipMemcpyDeviceToHost, st));
+    HIP_OK(ctx, hipStreamSynchronize(st));
+    for (int32_t k = 0; k < nc; ++k) {
+        if (st_in[k] != QMI_OK)
+            for (int64_t i = b->offsets[k]; i < b->offsets[k + 1]; ++i) y_out[i] = NAN;
+        if (status_out) status_out[k] = st_in[k];
+    }
+    return QMI_OK;
+}
+
+}  // namespace
+
+int qmi_preprocess(qmi_ctx* ctx, const qmi_batch* batch, const qmi_preprocess_params* params,
+                   int64_t* offsets_out, double* t_out, double* y_out, double* e_out,
+                   int32_t* status_out, uint8_t* detrended_out) {
+    if (!ctx) return QMI_EINVAL;
+    try {
+        return preprocess_call(ctx, batch, params, offsets_out, t_out, y_out, e_out, status_out,
+                               detrended_out);
+    } catch (...) {
+        set_err(ctx, "internal exception");
+        return QMI_EINTERNAL;
+    }
+}
+
+int qmi_whiten(qmi_ctx* ctx, const qmi_batch* batch, const double* periods, int32_t window,
+               double* y_out, int32_t* status_out) {
+    if (!ctx) return QMI_EINVAL;
+    try {
+        return whiten_call(ctx, batch, periods, window, y_out, status_out);
     } catch (...) {
         set_err(ctx, "internal exception");
         return QMI_EINTERNAL;

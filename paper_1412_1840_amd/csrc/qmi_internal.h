@@ -118,6 +118,24 @@ hipError_t launch_bands_best(hipStream_t st, const CurveParams* cp, int n_curves
                              const double* score, const double* score2, int score_kind,
                              const BandsDev& bd, DevResult* res);
 
+// Preprocessing and whitening (qmi_prep.hip).
+struct PrepDev {
+    int32_t error_cut, detrend, min_samples, pad;
+    const int32_t* status_in;  // [curve] host validation (nonzero: skip the curve)
+    int32_t* counts;           // [curve] samples kept
+    int32_t* status;           // [curve] QMI_OK or QMI_EINVAL (too short)
+    uint8_t* detrended;        // [curve] 1 if the chi^2 line was subtracted
+    double* t_out;             // kept samples, compacted inside each curve's input span
+    double* y_out;
+    double* e_out;
+};
+size_t whiten_lds(int max_n);
+hipError_t launch_prep(hipStream_t st, int n_curves, const int64_t* offsets, const double* t,
+                       const double* y, const double* e, const PrepDev& pd);
+hipError_t launch_whiten(hipStream_t st, int n_curves, int max_n, const int64_t* offsets,
+                         const double* t, const double* y, const double* periods, int window,
+                         const int32_t* status, double* y_out);
+
 // Launchers (qmi_kernels.hip).  All launch on `st` and return hipGetLastError().
 hipError_t launch_prologue(hipStream_t st, CurveParams* cp, int n_curves, int max_n,
                            const double* t, const double* y, const double* e);

@@ -42,7 +42,7 @@ MAX_TRIALS = 1024
 SYMBOLS = ("qmi_create", "qmi_destroy", "qmi_last_error", "qmi_set_option", "qmi_get_stats",
            "qmi_periodogram", "qmi_best_period", "qmi_periodogram_dev", "qmi_best_period_dev",
            "qmi_discriminate", "qmi_calibrate", "qmi_serve_start", "qmi_submit", "qmi_poll",
-           "qmi_serve_stop", "qmi_bands_best_period")
+           "qmi_serve_stop", "qmi_bands_best_period", "qmi_preprocess", "qmi_whiten")
 SNR_EDGES = (0.0, 1.5, 2.0, 2.5, 3.5, 5.0, 10.0, 20.0, math.inf)
 
 
@@ -73,6 +73,11 @@ class Bands(ctypes.Structure):
                 ("n_grid", ctypes.c_int32), ("n_bands", ctypes.c_int32),
                 ("n_keep", ctypes.c_int32), ("n_trials", ctypes.c_int32),
                 ("score", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class PreprocessParams(ctypes.Structure):
+    _fields_ = [("error_cut", ctypes.c_int32), ("min_samples", ctypes.c_int32),
+                ("detrend", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Thresholds(ctypes.Structure):
@@ -131,6 +136,10 @@ def lib() -> ctypes.CDLL:
             f.restype = ctypes.c_int
         L.qmi_bands_best_period.argtypes = [V, P(Batch), P(KernelParams), P(Bands), V, V, V]
         L.qmi_bands_best_period.restype = ctypes.c_int
+        L.qmi_preprocess.argtypes = [V, P(Batch), P(PreprocessParams), V, V, V, V, V, V]
+        L.qmi_preprocess.restype = ctypes.c_int
+        L.qmi_whiten.argtypes = [V, P(Batch), V, I32, V, V]
+        L.qmi_whiten.restype = ctypes.c_int
         L.qmi_discriminate.argtypes = [V, I32, V, P(Thresholds), V]
         L.qmi_discriminate.restype = ctypes.c_int
         L.qmi_calibrate.argtypes = [V, V, V, I32, V, I32, I32, V, V, V, V]
@@ -303,6 +312,38 @@ class Context:
                                                 ctypes.byref(bp), res.ctypes.data,
                                                 trials.ctypes.data, scores.ctypes.data))
         return res, trials, scores
+
+    def preprocess(self, offsets, t, y, e, error_cut: bool = True, min_samples: int = 50,
+                   detrend: bool = True):
+        """Sec. 5.2 preprocessing: (offsets, t, y, e, status, detrended) of the new batch."""
+        t, y = _f64(t), _f64(y)
+        e = None if e is None else _f64(e)
+        b, off = self._batch(offsets, t, y, e)
+        nc = b.n_curves
+        oo = np.zeros(nc + 1, np.int64)
+        to, yo = np.empty(len(t)), np.empty(len(t))
+        eo = None if e is None else np.empty(len(t))
+        st = np.zeros(nc, np.int32)
+        det = np.zeros(nc, np.uint8)
+        pp = PreprocessParams(int(bool(error_cut)), int(min_samples), int(bool(detrend)), 0)
+        self._check(lib().qmi_preprocess(self._h, ctypes.byref(b), ctypes.byref(pp), oo.ctypes.data,
+                                         to.ctypes.data, yo.ctypes.data, _addr(eo), st.ctypes.data,
+                                         det.ctypes.data))
+        m = int(oo[-1])
+        return oo, to[:m], yo[:m], (None if eo is None else eo[:m]), st, det.astype(bool)
+
+    def whiten(self, offsets, t, y, periods, window: int = 30):
+        """Sec. 7.1 whitening at the given per-curve periods: (y_whitened, status)."""
+        t, y = _f64(t), _f64(y)
+        b, off = self._batch(offsets, t, y, None)
+        p = _f64(periods)
+        if len(p) != b.n_curves:
+            raise ValueError("one period per curve")
+        out = np.empty(len(y))
+        st = np.zeros(b.n_curves, np.int32)
+        self._check(lib().qmi_whiten(self._h, ctypes.byref(b), p.ctypes.data, int(window),
+                                     out.ctypes.data, st.ctypes.data))
+        return out, st
 
     def periodogram_dev(self, offsets, t, y, e, freqs, score_out, sigma_t: float,
                         sigma_y: float = SIGMA_SILVERMAN, score: int = SCORE_QMI,

@@ -55,6 +55,7 @@ def test_struct_sizes():
     assert ctypes.sizeof(qmi.Search) == 32
     assert ctypes.sizeof(qmi.Thresholds) == 24
     assert ctypes.sizeof(qmi.Bands) == 40
+    assert ctypes.sizeof(qmi.PreprocessParams) == 16
     assert qmi.RESULT_DTYPE.itemsize == 96
 
 
