@@ -38,7 +38,8 @@ def parse():
                     help="curves timed one per call for the plain per-curve path (0: skip)")
     ap.add_argument("--cpu-sample", type=int, default=8,
                     help="curves of the CPU-oracle baseline sample (0: skip)")
-    ap.add_argument("--cpu-freqs", type=int, default=512)
+    ap.add_argument("--cpu-freqs", type=int, default=4096,
+                    help="coarse frequencies of the CPU-oracle sample (about 10 s on 16 cores)")
     ap.add_argument("--no-probe", action="store_true", help="skip the VALU rate probe")
     ap.add_argument("--serve-requests", type=int, default=1000,
                     help="requests of the serving measurement (0: skip)")

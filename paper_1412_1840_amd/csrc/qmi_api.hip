@@ -1425,7 +1425,9 @@ int qmi_serve_start(qmi_ctx* ctx, const qmi_kernel_params* kp, const qmi_search*
             for (qmi_ctx* c : S->lanes) qmi_destroy(c);
             return rc;
         }
-        lc->use_graph = ctx->use_graph;
+        // Serving batches differ in composition, so a captured graph would almost never be
+        // replayed: the lanes launch eagerly.
+        lc->use_graph = false;
         S->lanes.push_back(lc);
     }
     ctx->serve = std::move(S);

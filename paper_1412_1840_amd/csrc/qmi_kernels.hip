@@ -260,9 +260,19 @@ ksum_kernel(const CurveParams* __restrict__ cp, const R* __restrict__ K, R* __re
         const int nrows = min(ROWS, max(0, (n - base - w + kWaves - 1) / kWaves));
         int cnt = (j - base - w + kWaves - 1) / kWaves;
         cnt = cnt < 0 ? 0 : (cnt > nrows ? nrows : cnt);
+        // The wave's ROWS values of column j are one aligned 128-byte run of row j of the
+        // permuted table (always inside the row: kperm(base + w) + ROWS <= base + PASS <= npad);
+        // read it whole with 16-byte loads, then add its first cnt values in row order.
         const R* kr = K + P.koff + (int64_t)j * P.npad + kperm(base + w);
+        R kv[ROWS];
+        const float4* kr4 = reinterpret_cast<const float4*>(kr);
+#pragma unroll
+        for (int q = 0; q < (int)(ROWS * sizeof(R) / 16); ++q)
+            *reinterpret_cast<float4*>(&kv[q * 16 / sizeof(R)]) = kr4[q];
         R acc[4] = {R(0), R(0), R(0), R(0)};
-        for (int m = 0; m < cnt; ++m) acc[m & 3] = fma(kr[m], R(1), acc[m & 3]);
+#pragma unroll
+        for (int m = 0; m < ROWS; ++m)
+            if (m < cnt) acc[m & 3] = fma(kv[m], R(1), acc[m & 3]);
         ks[P.ksoff + e] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     }
 }

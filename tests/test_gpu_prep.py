@@ -97,7 +97,8 @@ def test_whiten_maximum_length_and_bad_period(ctx):
     t = synth.seasonal_times(rng, 8192, baseline=30000.0)
     y = np.sin(2 * math.pi * t / 2.9) + rng.normal(0, 0.3, 8192)
     t2, y2 = t[:100], y[:100]
-    b = synth.pack([synth.Curve(t, y, None, True), synth.Curve(t2, y2, None, True)])
+    b = synth.pack([synth.Curve(t, y, np.ones_like(t), True),
+                    synth.Curve(t2, y2, np.ones_like(t2), True)])
     yw, st = ctx.whiten(b.offsets, b.t, b.y, [2.9, -1.0])
     assert st[0] == 0 and st[1] == qmi.EINVAL
     assert np.array_equal(yw[:8192], O.whiten(t, y, 2.9))
