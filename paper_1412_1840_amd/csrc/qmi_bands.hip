@@ -136,33 +136,56 @@ bands_prep_kernel(const CurveParams* __restrict__ cp, const double* __restrict__
     }
 }
 
-// Spectral window S(f_k) = (sum cos 2 pi p)^2 + (sum sin 2 pi p)^2 over a kept band's times, with
-// the phase p = x - rint(x), x = f_k t (FP64).  One thread per grid point; blocks walk
-// (curve, band, grid tile).
+// Spectral window S(f_k) = |sum_i exp(2 pi i f_k t_i)|^2 over a kept band's times (FP64).  A
+// thread owns kWinRun consecutive grid points: per sample it forms exp(2 pi i f t) at its first
+// point from the folded phase x - rint(x), x = f t, and steps to the next points by multiplying
+// with exp(2 pi i df t) (one complex product per point instead of a sine and a cosine; the
+// rounding error grows by a few ulp per step).  Blocks walk (curve, band, grid tile).
+constexpr int kWinRun = 16;
+
+__device__ __forceinline__ void cis2pi(double x, double& c, double& s) {
+    const double p = x - rint(x);
+    sincospi(2.0 * p, &s, &c);
+}
+
 __global__ void __launch_bounds__(kWindowBlock)
 window_kernel(const CurveParams* __restrict__ cp, int tiles, BandsDev bd) {
-    extern __shared__ double tb[];
+    extern __shared__ double2 step[];  // [cnt] (cos, sin) of 2 pi df t_i
     const int64_t blk = blockIdx.x;
     const int tile = (int)(blk % tiles);
     const int64_t cb = blk / tiles;  // curve * n_keep + band
     const int c = (int)(cb / bd.n_keep);
-    const int k = tile * kWindowBlock + threadIdx.x;
     const int cnt = (cp[c].status == 0) ? bd.band_cnt[cb] : 0;
     const double* bt = bd.band_t + cb * bd.stride;
-    for (int i = threadIdx.x; i < cnt; i += kWindowBlock) tb[i] = bt[i];
-    __syncthreads();
-    if (k >= bd.n_grid) return;
-    const double f = band_grid_f(bd.f_lo, bd.df, k);
-    double sc = 0.0, ss = 0.0;
-    for (int i = 0; i < cnt; ++i) {
-        const double x = f * tb[i];
-        const double p = x - rint(x);
-        double s, co;
-        sincospi(2.0 * p, &s, &co);
-        sc += co;
-        ss += s;
+    for (int i = threadIdx.x; i < cnt; i += kWindowBlock) {
+        double sc, ss;
+        cis2pi(bd.df * bt[i], sc, ss);
+        step[i] = make_double2(sc, ss);
     }
-    bd.S[cb * bd.n_grid + k] = sc * sc + ss * ss;
+    __syncthreads();
+    const int k0 = (tile * kWindowBlock + threadIdx.x) * kWinRun;
+    if (k0 >= bd.n_grid) return;
+    const double f0 = band_grid_f(bd.f_lo, bd.df, k0);
+    double re[kWinRun], im[kWinRun];
+#pragma unroll
+    for (int g = 0; g < kWinRun; ++g) re[g] = im[g] = 0.0;
+    for (int i = 0; i < cnt; ++i) {
+        double zr, zi;
+        cis2pi(f0 * bt[i], zr, zi);
+        const double2 w = step[i];
+#pragma unroll
+        for (int g = 0; g < kWinRun; ++g) {
+            re[g] += zr;
+            im[g] += zi;
+            const double nr = zr * w.x - zi * w.y;
+            zi = zr * w.y + zi * w.x;
+            zr = nr;
+        }
+    }
+    double* out = bd.S + cb * bd.n_grid;
+#pragma unroll
+    for (int g = 0; g < kWinRun; ++g)
+        if (k0 + g < bd.n_grid) out[k0 + g] = re[g] * re[g] + im[g] * im[g];
 }
 
 // Candidate key of grid point k: 1 + the bits of S(k) (S >= 0, so the order of the keys is the
@@ -432,10 +455,11 @@ hipError_t launch_bands(hipStream_t st, const CurveParams* cp, int n_curves, int
     bands_prep_kernel<<<n_curves, kBandsBlock, bands_prep_lds(max_n), st>>>(cp, t, y, bd);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int tiles = (bd.n_grid + kWindowBlock - 1) / kWindowBlock;
+    const int per_block = kWindowBlock * kWinRun;
+    const int tiles = (bd.n_grid + per_block - 1) / per_block;
     const int64_t blocks = (int64_t)n_curves * bd.n_keep * tiles;
     if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
-    window_kernel<<<(unsigned)blocks, kWindowBlock, (size_t)bd.stride * 8, st>>>(cp, tiles, bd);
+    window_kernel<<<(unsigned)blocks, kWindowBlock, (size_t)bd.stride * 16, st>>>(cp, tiles, bd);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     trials_kernel<<<(unsigned)((int64_t)n_curves * bd.n_keep), kTrialsBlock, 0, st>>>(cp, bd);

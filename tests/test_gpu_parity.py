@@ -496,3 +496,20 @@ def test_survey_batch_best_period_matches_oracle_full_search():
     print("discriminator: %d of %d agree (%d within the score tolerance of a threshold)"
           % (agree, len(recs), len(near)))
     assert all(got[k] == want[k] for k in range(len(recs)) if k not in near)
+
+
+def test_empty_batches_on_every_entry_point(ctx):
+    """A batch of zero curves is valid everywhere and produces empty outputs."""
+    z = np.zeros(0)
+    off = [0]
+    sc, ips, ipy, st = ctx.periodogram(off, z, z, z, [0.1, 0.2], 0.3, want_ips=True)
+    assert sc.shape == (0, 2) and ips.shape == (0, 2, 3) and st.shape == (0,)
+    res, coarse = ctx.best_period(off, z, z, z, 0.3, want_coarse=True, **SEARCH)
+    assert len(res) == 0 and coarse.shape == (0, SEARCH["n_coarse"])
+    res, trials, scores = ctx.bands_best_period(off, z, z, z, 0.3)
+    assert len(res) == 0 and trials.shape == (0, 450)
+    oo, to, yo, eo, st, det = ctx.preprocess(off, z, z, z)
+    assert list(oo) == [0] and len(to) == 0 and len(st) == 0
+    yw, st = ctx.whiten(off, z, z, np.zeros(0))
+    assert len(yw) == 0 and len(st) == 0
+    assert len(qmi.discriminate(np.zeros(0, qmi.RESULT_DTYPE), O.SNR_EDGES, [0.5] * 8)) == 0
