@@ -45,12 +45,12 @@ def parse():
                     help="requests of the serving measurement (0: skip)")
     ap.add_argument("--serve-load", type=float, default=0.5,
                     help="Poisson arrival rate as a fraction of the measured batch throughput")
-    ap.add_argument("--serve-batch", type=int, default=256)
-    ap.add_argument("--serve-inflight", type=int, default=2)
+    ap.add_argument("--serve-batch", type=int, default=64)
+    ap.add_argument("--serve-inflight", type=int, default=3)
     ap.add_argument("--serve-sweep", default="",
                     help="comma-separated loads (fractions of the saturated serving throughput, "
                          "measured first); replaces --serve-load")
-    ap.add_argument("--serve-warmup", type=int, default=0,
+    ap.add_argument("--serve-warmup", type=int, default=200,
                     help="requests served first and left out of the latency statistics")
     ap.add_argument("--tile", type=int, default=0,
                     help="force pair-kernel variant k-1 (0: autotuned)")
@@ -422,8 +422,9 @@ def main():
             sweep["loads"].append(r)
         serve = min(sweep["loads"], key=lambda r: abs(r["load"] - 0.5))
     elif a.serve_requests > 0:
-        serve = serving(qmi, synth, wl, st_, a.serve_load * value, a.serve_requests,
-                        a.serve_batch, a.serve_inflight, warmup=a.serve_warmup)
+        serve = serving(qmi, synth, wl, st_, a.serve_load * value,
+                        a.serve_requests + a.serve_warmup, a.serve_batch, a.serve_inflight,
+                        warmup=a.serve_warmup)
 
     line = {
         "metric": METRIC,

@@ -480,22 +480,26 @@ def test_survey_batch_best_period_matches_oracle_full_search():
     the discriminator's decisions."""
     gold, recs, curves, res = _golden_search("survey_batch", synth.survey_batch_curve)
     _compare_best(gold, recs, curves, res, "survey batch")
-    # Discriminator: thresholds calibrated by the oracle on its own scores, then the decision of
-    # every curve from the GPU result (score at f_best, pSNR) against the oracle's decision.
+    # Discriminator: thresholds calibrated by the oracle on its own scores of the curves with
+    # k mod 4 in {0, 1}; then, for the other curves, the decision from the GPU result (score at
+    # f_best, pSNR) against the oracle's decision.  Curves whose oracle score lies within the
+    # score tolerance of their bin's threshold may go either way and are counted separately.
     psn = [O.psnr(c.y, c.e) for c in curves]
     for r, p in zip(res, psn):
         assert r["psnr"] == pytest.approx(p, rel=1e-12)
-    cal = O.calibrate_thresholds([g["score"] for g in recs], psn, [g["periodic"] for g in recs],
-                                 n_points=5000)
+    train = [k for k, g in enumerate(recs) if g["k"] % 4 < 2]
+    test = [k for k, g in enumerate(recs) if g["k"] % 4 >= 2]
+    cal = O.calibrate_thresholds([recs[k]["score"] for k in train], [psn[k] for k in train],
+                                 [recs[k]["periodic"] for k in train], n_points=5000)
     th = [x if math.isfinite(x) else 1e300 for x in cal["th"]]
     got = qmi.discriminate(res, O.SNR_EDGES, th)
     want = [O.discriminate(g["score"], p, th) for g, p in zip(recs, psn)]
-    near = [k for k, (g, p) in enumerate(zip(recs, psn))
-            if abs(g["score"] - th[O.snr_bin(p)]) <= QMI_TOL * abs(g["score"])]
-    agree = sum(1 for k in range(len(recs)) if got[k] == want[k])
-    print("discriminator: %d of %d agree (%d within the score tolerance of a threshold)"
-          % (agree, len(recs), len(near)))
-    assert all(got[k] == want[k] for k in range(len(recs)) if k not in near)
+    near = [k for k in test if O.snr_bin(psn[k]) >= 0 and
+            abs(recs[k]["score"] - th[O.snr_bin(psn[k])]) <= QMI_TOL * abs(recs[k]["score"])]
+    agree = sum(1 for k in test if got[k] == want[k])
+    print("discriminator: %d of %d held-out curves agree (%d within the score tolerance of a "
+          "threshold)" % (agree, len(test), len(near)))
+    assert all(got[k] == want[k] for k in test if k not in near)
 
 
 def test_empty_batches_on_every_entry_point(ctx):
