@@ -59,6 +59,8 @@ struct qmi_ctx {
         kPPer, kNumBufs
     };
     Buf bufs[kNumBufs];
+    static_assert(kNumBufs <= 64, "one bit per buffer in in_use");
+    uint64_t in_use = 0;  // bit per buffer ensured by the current operation
     // Graph cache (device section of one planned group).
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -93,11 +95,49 @@ void set_err(qmi_ctx* ctx, const char* fmt, ...) {
         }                                                                                  \
     } while (0)
 
+void drop_graph(qmi_ctx* ctx) {
+    // Any captured graph refers to buffer addresses that are about to change.
+    if (ctx->graph_exec) {
+        (void)hipGraphExecDestroy(ctx->graph_exec);
+        ctx->graph_exec = nullptr;
+    }
+    if (ctx->graph) {
+        (void)hipGraphDestroy(ctx->graph);
+        ctx->graph = nullptr;
+    }
+    ctx->graph_key.clear();
+}
+
+int free_buf(qmi_ctx* ctx, int id) {
+    Buf& b = ctx->bufs[id];
+    if (!b.p) return QMI_OK;
+    HIP_OK(ctx, hipStreamSynchronize(ctx->stream));
+    HIP_OK(ctx, hipFree(b.p));
+    ctx->allocated -= b.bytes;
+    b.p = nullptr;
+    b.bytes = 0;
+    drop_graph(ctx);
+    return QMI_OK;
+}
+
+// Buffers ensured since the last begin_use() are in use by the current operation; the others
+// hold stale contents of earlier operations and may be released to stay inside the budget.
+void begin_use(qmi_ctx* ctx) { ctx->in_use = 0; }
+
 int ensure(qmi_ctx* ctx, int id, size_t bytes) {
     Buf& b = ctx->bufs[id];
     if (bytes == 0) bytes = 256;
+    ctx->in_use |= 1ull << id;
     if (b.bytes >= bytes) return QMI_OK;
     size_t want = bytes + bytes / 8;  // some headroom for the next call
+    if (ctx->allocated - b.bytes + want > ctx->budget) {
+        // Release buffers the current operation does not use before giving up.
+        for (int k = 0; k < qmi_ctx::kNumBufs; ++k)
+            if (!(ctx->in_use & (1ull << k))) {
+                const int rc = free_buf(ctx, k);
+                if (rc) return rc;
+            }
+    }
     if (ctx->allocated - b.bytes + want > ctx->budget) want = bytes;
     if (ctx->allocated - b.bytes + want > ctx->budget) {
         set_err(ctx, "HBM budget exceeded: need %zu more bytes (budget %zu)",
@@ -105,21 +145,8 @@ int ensure(qmi_ctx* ctx, int id, size_t bytes) {
         return QMI_ENOMEM;
     }
     if (b.p) {
-        HIP_OK(ctx, hipStreamSynchronize(ctx->stream));
-        HIP_OK(ctx, hipFree(b.p));
-        ctx->allocated -= b.bytes;
-        b.p = nullptr;
-        b.bytes = 0;
-        // Any captured graph refers to the old address.
-        if (ctx->graph_exec) {
-            (void)hipGraphExecDestroy(ctx->graph_exec);
-            ctx->graph_exec = nullptr;
-        }
-        if (ctx->graph) {
-            (void)hipGraphDestroy(ctx->graph);
-            ctx->graph = nullptr;
-        }
-        ctx->graph_key.clear();
+        const int rc = free_buf(ctx, id);
+        if (rc) return rc;
     }
     HIP_OK(ctx, hipMalloc(&b.p, want));
     b.bytes = want;
@@ -237,7 +264,8 @@ struct CallSpec {
 // Per-curve device bytes of the bands method's own buffers (time-ordered copies, band times,
 // spectral windows, trial lists).
 size_t bands_bytes(int64_t n, const qmi_bands& bp) {
-    const int64_t stride = (n + bp.n_bands - 1) / bp.n_bands;
+    // Band rows are as long as the group's longest curve needs; count the longest possible.
+    const int64_t stride = (QMI_MAX_N + bp.n_bands - 1) / bp.n_bands;
     size_t b = (size_t)n * 16;
     b += (size_t)bp.n_keep * (size_t)(stride * 8 + 8);
     b += (size_t)bp.n_keep * (size_t)bp.n_grid * 8;
@@ -257,7 +285,9 @@ int plan_groups(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, std::vecto
         set_err(ctx, "HBM budget too small");
         return QMI_ENOMEM;
     }
-    const size_t avail = ctx->budget - fixed;
+    // Buffers may carry 1/8 of growth headroom (see ensure), so a group is sized to fit even when
+    // every buffer it uses has it.
+    const size_t avail = (ctx->budget - fixed) / 9 * 8;
     Group g{0, 0, 0, 0};
     size_t used = 0;
     for (int32_t k = 0; k < b->n_curves; ++k) {
@@ -295,6 +325,7 @@ void record(qmi_ctx* ctx) {
 template <typename R>
 int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group& g,
               std::vector<int32_t>& pair_event_idx) {
+    begin_use(ctx);
     const int32_t nc = g.c1 - g.c0;
     const int64_t ns = g.s1 - g.s0;
     const bool fp64 = std::is_same<R, double>::value;
@@ -1173,6 +1204,7 @@ int preprocess_call(qmi_ctx* ctx, const qmi_batch* b, const qmi_preprocess_param
                 if (!(b->e[i] > 0.0)) st_in[k] = QMI_EINVAL;  // chi^2 weights need e > 0
     }
     HIP_OK(ctx, hipSetDevice(ctx->device));
+    begin_use(ctx);
     int max_n = 0;
     if ((rc = upload_batch(ctx, b, st_in, &max_n)) != QMI_OK) return rc;
     const int ids[] = {qmi_ctx::kPTo, qmi_ctx::kPYo, qmi_ctx::kPEo};
@@ -1242,6 +1274,7 @@ int whiten_call(qmi_ctx* ctx, const qmi_batch* b, const double* periods, int32_t
         if (!(periods[k] > 0.0) || !std::isfinite(periods[k])) st_in[k] = QMI_EINVAL;
     }
     HIP_OK(ctx, hipSetDevice(ctx->device));
+    begin_use(ctx);
     int max_n = 0;
     if ((rc = upload_batch(ctx, b, st_in, &max_n)) != QMI_OK) return rc;
     if ((rc = ensure(ctx, qmi_ctx::kPYo, std::max<int64_t>(ns, 1) * 8)) != QMI_OK) return rc;

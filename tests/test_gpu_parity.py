@@ -517,3 +517,71 @@ def test_empty_batches_on_every_entry_point(ctx):
     yw, st = ctx.whiten(off, z, z, np.zeros(0))
     assert len(yw) == 0 and len(st) == 0
     assert len(qmi.discriminate(np.zeros(0, qmi.RESULT_DTYPE), O.SNR_EDGES, [0.5] * 8)) == 0
+
+
+def test_benchmark_launch_configuration_sampled():
+    """The benchmark's own call: all 4096 survey-batch curves in one qmi_best_period_dev launch
+    sequence on device-resident inputs (XCD-grouped blocks, autotuned variant).  Sampled coarse
+    scores of sampled curves against the oracle, and every curve that has a stored oracle search
+    against it."""
+    import json
+    import os
+
+    import torch
+
+    b = synth.make_batch("survey_batch", range(4096))
+    wl = synth.WORKLOADS["survey_batch"]
+    kw = {k: wl[k] for k in ("f_min", "f_max", "n_coarse", "top_k", "n_fine")}
+    dev = torch.device("cuda:0")
+    T, Y, E = (torch.from_numpy(a).to(dev) for a in (b.t, b.y, b.e))
+    coarse = torch.empty((4096, kw["n_coarse"]), dtype=torch.float64, device=dev)
+    with qmi.Context(0) as c:
+        c.best_period_dev(b.offsets, T, Y, E, wl["sigma_t"], **kw)  # first call tunes
+        res = c.best_period_dev(b.offsets, T, Y, E, wl["sigma_t"], coarse_out=coarse, **kw)
+        variant = c.stats()["pair_variant"]
+    torch.cuda.synchronize()
+    assert np.all(res["status"] == 0)
+    print("variant %d" % variant)
+    rng = np.random.default_rng(12)
+    grid = O.linear_grid(kw["f_min"], kw["f_max"], kw["n_coarse"])
+    for k in np.sort(rng.choice(4096, 24, replace=False)):
+        cv = b.curve(int(k))
+        idx = np.sort(rng.choice(len(grid), 48, replace=False))
+        got = coarse[int(k), torch.from_numpy(idx).to(dev)].cpu().numpy()
+        ref = O.qmi(oracle_ips(cv, grid[idx]))
+        assert floor_rel(got, ref).max() <= QMI_TOL, k
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "survey_batch_oracle.json")
+    for g in json.load(open(path))["curves"]:
+        r = res[g["k"]]
+        assert (r["coarse_index"], r["fine_index"]) == (g["coarse_index"], g["fine_index"]), g["k"]
+        assert r["f_best"] == g["f_best"]
+
+
+def test_small_hbm_budget_splits_the_batch_into_groups():
+    """A context whose HBM budget holds only a few curves at a time plans several groups (and
+    reuses its buffers across them); the results equal those of one group, bit for bit, for the
+    search, the periodogram and the bands front end.  A curve that alone exceeds the budget is a
+    call-level QMI_ENOMEM."""
+    curves = [synth.survey_batch_curve(k, n=n) for k, n in
+              enumerate([300, 800, 120, 1000, 450, 640, 999, 301, 77])]
+    b = pack(curves)
+    kw = dict(f_min=1e-3, f_max=10.0, n_coarse=3000, top_k=3, n_fine=64)
+    freqs = O.linear_grid(1e-3, 10.0, 700)
+    with qmi.Context(0) as big, qmi.Context(0, budget_bytes=8 << 20) as small:
+        for c in (big, small):  # one variant for both (the autotuner may not see every group)
+            c.set_option(qmi.OPT_TILE, 2)
+        r1, c1 = big.best_period(b.offsets, b.t, b.y, b.e, 0.3, want_coarse=True, **kw)
+        r2, c2 = small.best_period(b.offsets, b.t, b.y, b.e, 0.3, want_coarse=True, **kw)
+        assert r1.tobytes() == r2.tobytes() and np.array_equal(c1, c2)
+        s1 = big.periodogram(b.offsets, b.t, b.y, b.e, freqs, 0.3)[0]
+        s2 = small.periodogram(b.offsets, b.t, b.y, b.e, freqs, 0.3)[0]
+        assert np.array_equal(s1, s2)
+        q1 = big.bands_best_period(b.offsets, b.t, b.y, b.e, 0.3, n_trials=40, n_grid=5000)
+        q2 = small.bands_best_period(b.offsets, b.t, b.y, b.e, 0.3, n_trials=40, n_grid=5000)
+        assert q1[0].tobytes() == q2[0].tobytes()
+        assert np.array_equal(q1[1], q2[1], equal_nan=True)
+    with qmi.Context(0, budget_bytes=3 << 20) as tiny:
+        with pytest.raises(qmi.QMIError) as ei:
+            tiny.best_period(b.offsets, b.t, b.y, b.e, 0.3, **kw)
+        assert ei.value.code == qmi.ENOMEM
