@@ -45,8 +45,8 @@ def parse():
                     help="requests of the serving measurement (0: skip)")
     ap.add_argument("--serve-load", type=float, default=0.5,
                     help="Poisson arrival rate as a fraction of the measured batch throughput")
-    ap.add_argument("--serve-batch", type=int, default=64)
-    ap.add_argument("--serve-inflight", type=int, default=3)
+    ap.add_argument("--serve-batch", type=int, default=256)
+    ap.add_argument("--serve-inflight", type=int, default=2)
     ap.add_argument("--serve-sweep", default="",
                     help="comma-separated loads (fractions of the saturated serving throughput, "
                          "measured first); replaces --serve-load")

@@ -49,7 +49,7 @@ extern "C" {
 #define QMI_ENOMEM (-2)      /* device memory: a single curve does not fit the HBM budget */
 #define QMI_EDEVICE (-3)     /* HIP runtime error; text in qmi_last_error */
 #define QMI_EDEGENERATE (-4) /* width rule gives zero (per-curve status only) */
-#define QMI_EAGAIN (-5)      /* serving: admission budget full, try again later */
+#define QMI_EAGAIN (-5)      /* serving: admission budget full, submit again later */
 #define QMI_EINTERNAL (-6)   /* internal error */
 
 /* Limits. */
@@ -322,13 +322,20 @@ int qmi_calibrate(const double *scores, const double *psnr, const uint8_t *truth
                   double *f1_out, double *precision_out, double *recall_out);
 
 /*
- * Serving (continuous batching).  qmi_submit copies one curve (host arrays of n samples) into
- * library-owned pinned staging and queues it with a caller tag; it returns QMI_EAGAIN when the
- * admission budget (queued plus in-flight device memory) is full.  A background host thread admits
- * queued requests into device launches as memory frees up, with up to max_inflight launches
- * overlapping on the device.  qmi_poll moves up to max completed results (with their tags) into
- * out / tags and returns their count (waiting up to timeout_us microseconds for at least one).
- * Every request uses the kernel parameters and search given to qmi_serve_start.
+ * Serving (continuous batching).  qmi_serve_start starts max_inflight (1..8) worker threads, each
+ * with a private context and stream on ctx's device (ctx's HBM budget split between them), and
+ * fixes the kernel parameters and search of every request.  qmi_submit copies one curve (host
+ * arrays of n samples; e nullable) into a host-side queue with a caller tag and returns QMI_OK, or
+ * QMI_EAGAIN when the queued requests' estimated device footprint would exceed admit_budget_bytes
+ * (0: half of ctx's budget); the caller owns t / y / e and may reuse them at once.  A free worker
+ * takes queued requests in arrival order while they fit its share of the admission budget, at
+ * most max_batch of them, runs them as one qmi_best_period call on its stream, and posts the
+ * results; the launches of different workers overlap on the device.  A request's result does not
+ * depend on the other requests it was batched with (bitwise).  qmi_poll moves up to max completed
+ * results (with their tags) into out / tags and returns their count, waiting up to timeout_us
+ * microseconds for at least one.  qmi_serve_stop finishes the queued requests, joins the workers
+ * and discards results not yet polled.  A context serves at most one stream of requests at a time;
+ * its other entry points stay usable meanwhile.
  */
 int qmi_serve_start(qmi_ctx *ctx, const qmi_kernel_params *kp, const qmi_search *search,
                     size_t admit_budget_bytes, int32_t max_batch, int32_t max_inflight);

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqmi.so")
-SOURCES = ["qmi_kernels.hip", "qmi_bands.hip", "qmi_prep.hip", "qmi_api.hip"]
+SOURCES = ["qmi_kernels.hip", "qmi_search.hip", "qmi_bands.hip", "qmi_prep.hip", "qmi_api.hip"]
 PROBE = os.path.join(HERE, "valu_rates")
 ARCH = "gfx950"
 

@@ -440,9 +440,10 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
     CurveParams* dcp = dptr<CurveParams>(ctx, qmi_ctx::kCP);
     int32_t* dorder = dptr<int32_t>(ctx, qmi_ctx::kOrder);
     int64_t* drow = dptr<int64_t>(ctx, qmi_ctx::kRowStart);
-    HIP_OK(ctx, hipMemcpyAsync(dcp, cp.data(), nc * sizeof(CurveParams), hipMemcpyHostToDevice, st));
-    HIP_OK(ctx, hipMemcpyAsync(dorder, order.data(), nc * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    HIP_OK(ctx, hipMemcpyAsync(drow, row_start.data(), nc * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    const hipMemcpyKind h2d = hipMemcpyHostToDevice;
+    HIP_OK(ctx, hipMemcpyAsync(dcp, cp.data(), nc * sizeof(CurveParams), h2d, st));
+    HIP_OK(ctx, hipMemcpyAsync(dorder, order.data(), nc * sizeof(int32_t), h2d, st));
+    HIP_OK(ctx, hipMemcpyAsync(drow, row_start.data(), nc * sizeof(int64_t), h2d, st));
     const double* dfreqs = nullptr;
     if (cs.periodogram) {
         if (cs.dev_inputs) {
@@ -537,7 +538,8 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
     }
 
     // Pair-kernel variant: forced by QMI_OPT_TILE, else the autotuned choice for this length
-    // bucket (variant 0 until the bucket has been tuned; see the end of this function).
+    // bucket; until the bucket has been tuned (see the end of this function), variant 1 (4 waves
+    // per SIMD, 64-column chunks), the fastest on every length mix measured.
     std::vector<int32_t> lens;
     for (int32_t i = 0; i < nc; ++i)
         if (cp[i].status == QMI_OK) lens.push_back(cp[i].n);
@@ -548,7 +550,7 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
         while (bucket < 7 && (192 << bucket) <= med) ++bucket;
     }
     const int nvar = pair_variants<R>();
-    int variant = 0;
+    int variant = nvar > 1 ? 1 : 0;
     const bool fold32 = kp->precision == QMI_PREC_FOLD32;
     if (fold32) variant = kVariantFold32;
     else if (ctx->tile > 0) variant = (int)std::min<int64_t>(ctx->tile - 1, nvar - 1);
@@ -556,7 +558,8 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
     double group_items = 0.0;
     for (int32_t i = 0; i < nc; ++i)
         if (cp[i].status == QMI_OK) group_items += 0.5 * cp[i].n * (cp[i].n - 1.0) * (double)F1;
-    const bool tune_now = !fp64 && !fold32 && ctx->tile == 0 && ctx->tuned[bucket] < 0 && nvar > 1 &&
+    const bool tune_now = !fp64 && !fold32 && ctx->tile == 0 && ctx->tuned[bucket] < 0 &&
+                          nvar > 1 &&
                           group_items > 2e9;
     ctx->stats.pair_variant = variant;
 
@@ -586,7 +589,8 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
                 PairOut fo{fine, fine2, nullptr, score_kind, 0};
                 if (events) pair_event_idx.push_back(ctx->ev_used);
                 rec();
-                HIP_OK(ctx, launch_pairs<R>(st, dcp, dorder, nc, ff, t, K, rd, rp, ks, fo, variant));
+                HIP_OK(ctx,
+                       launch_pairs<R>(st, dcp, dorder, nc, ff, t, K, rd, rp, ks, fo, variant));
                 rec();
             }
             HIP_OK(ctx, launch_best(st, dcp, nc, coarse, coarse2, s->n_coarse, fine, fine2,
@@ -676,7 +680,8 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
                                            nc * F1 * 24, hipMemcpyDeviceToHost, st));
         }
         std::vector<CurveParams> cpo(nc);
-        HIP_OK(ctx, hipMemcpyAsync(cpo.data(), dcp, nc * sizeof(CurveParams), hipMemcpyDeviceToHost, st));
+        HIP_OK(ctx, hipMemcpyAsync(cpo.data(), dcp, nc * sizeof(CurveParams),
+                                   hipMemcpyDeviceToHost, st));
         HIP_OK(ctx, hipStreamSynchronize(st));
         for (int32_t i = 0; i < nc; ++i) {
             if (cs.ip_y_out) cs.ip_y_out[g.c0 + i] = cpo[i].status ? NAN : cpo[i].ipy;
@@ -944,7 +949,8 @@ void serve_worker(qmi_ctx* ctx, int lane) {
             if (take[i].has_e) std::copy(take[i].e.begin(), take[i].e.end(), e.begin() + off[i]);
             all_e = all_e && take[i].has_e;
         }
-        qmi_batch b{(int32_t)take.size(), off.data(), t.data(), y.data(), all_e ? e.data() : nullptr};
+        qmi_batch b{(int32_t)take.size(), off.data(), t.data(), y.data(),
+                    all_e ? e.data() : nullptr};
         std::vector<qmi_result> res(take.size());
         int rc = qmi_best_period(lc, &b, &S->kp, &S->search, res.data(), nullptr);
         std::lock_guard<std::mutex> lk(S->mu);

@@ -1,5 +1,6 @@
-// HIP kernels for gfx950 (MI355X): prologue (kernel widths, pSNR), magnitude Gram matrix, the
-// pair x frequency sums (the hot path), peak selection and best-of.
+// HIP kernels for gfx950 (MI355X): prologue (kernel widths, pSNR), magnitude Gram matrix, column
+// K sums and the pair x frequency sums (the hot path).  The peak search and best-of kernels are in
+// qmi_search.hip.
 //
 // Method: Protopapas et al., arXiv:1412.1840.  Gaussian kernel (Sec. 2), periodic kernel and the
 // warp identity ||u_f(z) - u_f(y)||^2 = 4 sin^2(pi f (z - y)) (Sec. 2.1), CKP and information
@@ -368,9 +369,9 @@ __device__ __forceinline__ void ladd(double* p, double v) {
 }
 
 // One term of the pair sums for row i of this wave and the current column j: the kernel value
-// g = exp2(-(d^2 + moff)) with d = h_s(i) h_c(j) - h_c(i) h_s(j) and moff = 0 (or +inf for a row that
-// is masked out, giving g = 0), added to a column partial T, the row sum G and a K-weighted column
-// partial J.
+// g = exp2(-(d^2 + moff)) with d = h_s(i) h_c(j) - h_c(i) h_s(j) and moff = 0 (or +inf for a row
+// that is masked out, giving g = 0), added to a column partial T, the row sum G and a K-weighted
+// column partial J.
 template <typename R>
 __device__ __forceinline__ void pair_term(R hc, R hs, R ux, R uy, R moff, R k, R& T, R& G, R& J) {
     const R pr = hc * uy;
@@ -384,13 +385,13 @@ __device__ __forceinline__ void pair_term(R hc, R hs, R ux, R uy, R moff, R k, R
 
 // One work item = (curve, kLanes frequency slots).  Accumulators per lane (one frequency), FP64:
 //   ST  = sum_{i<j} g_ij                 SJ  = sum_{i<j} K(i,j) g_ij - sum_{i<j} K(i,j)
-//   SCa = sum_{i<j} r_i g_ij             SCb = sum_{i<j} r_j g_ij
-// with g_ij = exp(-2 sin^2(pi f (t_i - t_j)) / sigma_t^2) and r_i = sum_k K(i,k).  A column's terms
-// over the wave's rows are summed in R in four interleaved partials (rows m mod 4) and folded into
-// FP64 per column; the r-weighted sums multiply R sums by FP64 row sums (exact products).  Where all
-// kernel values are 1 (coincident phases, f = 0) every R sum is exact: the column sums of g and of
-// the row sums are integers, and the K-weighted column sum equals, bit for bit, the precomputed
-// sum of K over the same rows in the same order, so that SJ is 0 and the scores come out exactly.
+//   SC  = sum_{i<j} (r_i + r_j) g_ij
+// with g_ij = exp(-2 sin^2(pi f (t_i - t_j)) / sigma_t^2) and r_i = sum_k K(i,k).  A column's
+// terms over the wave's rows are summed in R in four interleaved partials (rows m mod 4) and folded
+// into FP64 per column; the r-weighted sums multiply R sums by FP64 row sums.  Where all kernel
+// values are 1 (coincident phases, f = 0) every R sum is exact: the column sums of g and the row
+// sums are integers, and the K-weighted column sum equals, bit for bit, the precomputed sum of K
+// over the same rows in the same order, so that SJ is 0 and the scores come out exactly.
 // Variants (chosen by the host autotuner): WPE is the occupancy target in waves per SIMD (2: the
 // registers of 2 waves, no spills; 4: at most 128 VGPRs, so two workgroups share a CU), CH the
 // columns per LDS chunk.
@@ -515,7 +516,8 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
                     R T4[4] = {R(0), R(0), R(0), R(0)}, J4[4] = {R(0), R(0), R(0), R(0)};
 #pragma unroll
                     for (int m = 0; m < ROWS; ++m)
-                        pair_term<R>(ci[m], si[m], u.x, u.y, zero, kk[m], T4[m & 3], G[m], J4[m & 3]);
+                        pair_term<R>(ci[m], si[m], u.x, u.y, zero, kk[m], T4[m & 3], G[m],
+                                     J4[m & 3]);
                     const R Tq = (T4[0] + T4[1]) + (T4[2] + T4[3]);
                     const R Jq = (J4[0] + J4[1]) + (J4[2] + J4[3]);
                     const double Td = (double)Tq;
@@ -596,187 +598,6 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
         out.ips[obase * 3 + 1] = IPt;
         out.ips[obase * 3 + 2] = VC;
     }
-}
-
-// --------------------------------------------------------------------------------------------
-// Peaks: local maxima of the coarse scores, best top_k by (score desc, k asc), and their
-// refinement windows.  One block per curve.
-// --------------------------------------------------------------------------------------------
-
-constexpr int kPeakBlock = 256;
-
-__device__ __forceinline__ bool better(double qa, int ka, double qb, int kb) {
-    // a ranks before b: higher score, ties to lower index.  NaN never ranks.
-    if (!(qa == qa)) return false;
-    if (!(qb == qb)) return true;
-    return qa > qb || (qa == qb && ka < kb);
-}
-
-__device__ __forceinline__ double grid_f(double f0, double df, int k) {
-    return __dadd_rn(f0, __dmul_rn((double)k, df));
-}
-
-__global__ void __launch_bounds__(kPeakBlock)
-peaks_kernel(const CurveParams* __restrict__ cp, const double* __restrict__ coarse, int F,
-             double f0, double df, int top_k, int n_fine, PeakOut po) {
-    __shared__ double sq[kPeakBlock];
-    __shared__ int sk[kPeakBlock];
-    __shared__ int chosen[64];
-    const int c = blockIdx.x;
-    const double* q = coarse + (int64_t)c * F;
-    const bool ok = cp[c].status == 0;
-    // Coarse argmax (ties to lower k).
-    double bq = NAN;
-    int bk = 0x7fffffff;
-    if (ok)
-        for (int k = threadIdx.x; k < F; k += kPeakBlock)
-            if (better(q[k], k, bq, bk)) { bq = q[k]; bk = k; }
-    sq[threadIdx.x] = bq;
-    sk[threadIdx.x] = bk;
-    __syncthreads();
-    for (int s = kPeakBlock / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s && better(sq[threadIdx.x + s], sk[threadIdx.x + s], sq[threadIdx.x],
-                                      sk[threadIdx.x])) {
-            sq[threadIdx.x] = sq[threadIdx.x + s];
-            sk[threadIdx.x] = sk[threadIdx.x + s];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) po.argmax[c] = (sk[0] == 0x7fffffff) ? 0 : sk[0];
-    __syncthreads();
-    // Iterative selection of the top_k local maxima.
-    int count = 0;
-    for (int p = 0; p < top_k && ok; ++p) {
-        bq = NAN;
-        bk = 0x7fffffff;
-        for (int k = threadIdx.x; k < F; k += kPeakBlock) {
-            const double v = q[k];
-            bool peak;
-            if (F == 1) peak = (v == v);
-            else if (k == 0) peak = v >= q[1];
-            else if (k == F - 1) peak = v > q[k - 1];
-            else peak = v > q[k - 1] && v >= q[k + 1];
-            if (!peak) continue;
-            bool taken = false;
-            for (int a = 0; a < count; ++a) taken |= (chosen[a] == k);
-            if (!taken && better(v, k, bq, bk)) { bq = v; bk = k; }
-        }
-        sq[threadIdx.x] = bq;
-        sk[threadIdx.x] = bk;
-        __syncthreads();
-        for (int s = kPeakBlock / 2; s > 0; s >>= 1) {
-            if (threadIdx.x < s && better(sq[threadIdx.x + s], sk[threadIdx.x + s],
-                                          sq[threadIdx.x], sk[threadIdx.x])) {
-                sq[threadIdx.x] = sq[threadIdx.x + s];
-                sk[threadIdx.x] = sk[threadIdx.x + s];
-            }
-            __syncthreads();
-        }
-        const int kk = sk[0];
-        __syncthreads();
-        if (kk == 0x7fffffff) break;
-        if (threadIdx.x == 0) chosen[count] = kk;
-        __syncthreads();
-        ++count;
-    }
-    if (threadIdx.x == 0) {
-        po.npk[c] = count;
-        for (int p = 0; p < count; ++p) {
-            const int k = chosen[p];
-            int a = k - 1, b = k + 1;
-            if (F == 1) { a = 0; b = 0; }
-            else if (k == 0) { a = 0; b = 1; }
-            else if (k == F - 1) { a = F - 2; b = F - 1; }
-            const double lo = grid_f(f0, df, a), hi = grid_f(f0, df, b);
-            po.peak_k[(int64_t)c * top_k + p] = k;
-            po.win[((int64_t)c * top_k + p) * 2 + 0] = lo;
-            po.win[((int64_t)c * top_k + p) * 2 + 1] = (hi - lo) / (double)(n_fine - 1);
-        }
-    }
-}
-
-// --------------------------------------------------------------------------------------------
-// Best-of: highest refined score, ties to the lower frequency then the lower peak rank.
-// --------------------------------------------------------------------------------------------
-
-constexpr int kBestBlock = 256;
-
-__global__ void __launch_bounds__(kBestBlock)
-best_kernel(const CurveParams* __restrict__ cp, const double* __restrict__ coarse,
-            const double* __restrict__ coarse2, int F,
-            const double* __restrict__ fine, const double* __restrict__ fine2, int top_k,
-            int n_fine, int score_kind, double f0, double df, PeakOut po,
-            DevResult* __restrict__ res) {
-    __shared__ double sq[kBestBlock], sf[kBestBlock];
-    __shared__ int ss[kBestBlock];
-    const int c = blockIdx.x;
-    const CurveParams P = cp[c];
-    const int npk = (top_k > 0 && n_fine > 0 && P.status == 0) ? po.npk[c] : 0;
-    const int64_t S = (int64_t)top_k * n_fine;
-    double bq = NAN, bf = INFINITY;
-    int bs = 0x7fffffff;
-    for (int s = threadIdx.x; s < npk * n_fine; s += kBestBlock) {
-        const double v = fine[(int64_t)c * S + s];
-        if (!(v == v)) continue;
-        const int p = s / n_fine, m = s - p * n_fine;
-        const double* w = po.win + ((int64_t)c * top_k + p) * 2;
-        const double fr = __dadd_rn(w[0], __dmul_rn((double)m, w[1]));
-        bool b = !(bq == bq) || v > bq || (v == bq && (fr < bf || (fr == bf && s < bs)));
-        if (b) { bq = v; bf = fr; bs = s; }
-    }
-    sq[threadIdx.x] = bq;
-    sf[threadIdx.x] = bf;
-    ss[threadIdx.x] = bs;
-    __syncthreads();
-    for (int h = kBestBlock / 2; h > 0; h >>= 1) {
-        if (threadIdx.x < h) {
-            const double v = sq[threadIdx.x + h], fr = sf[threadIdx.x + h];
-            const int s = ss[threadIdx.x + h];
-            const double cq = sq[threadIdx.x], cf = sf[threadIdx.x];
-            const int cs = ss[threadIdx.x];
-            bool b = (v == v) && (!(cq == cq) || v > cq || (v == cq && (fr < cf || (fr == cf && s < cs))));
-            if (b) { sq[threadIdx.x] = v; sf[threadIdx.x] = fr; ss[threadIdx.x] = s; }
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x != 0) return;
-    DevResult r;
-    r.sigma_y = P.sigma_y;
-    r.psnr = P.psnr;
-    r.n = P.n;
-    r.status = P.status;
-    r.reserved = 0;
-    r.n_peaks = npk;
-    const int am = (P.status == 0) ? po.argmax[c] : 0;
-    r.coarse_argmax = am;
-    r.coarse_best = (P.status == 0) ? coarse[(int64_t)c * F + am] : NAN;
-    if (P.status != 0) {
-        r.f_best = r.period = r.score = r.score_qmi = r.score_nckp = NAN;
-        r.coarse_index = r.peak_rank = r.fine_index = -1;
-    } else if (npk == 0 || ss[0] == 0x7fffffff) {
-        r.f_best = grid_f(f0, df, am);
-        r.period = 1.0 / r.f_best;
-        r.score = r.coarse_best;
-        r.coarse_index = am;
-        r.peak_rank = -1;
-        r.fine_index = -1;
-        const double other = coarse2 ? coarse2[(int64_t)c * F + am] : NAN;
-        r.score_qmi = score_kind == 0 ? r.coarse_best : other;
-        r.score_nckp = score_kind == 0 ? other : r.coarse_best;
-    } else {
-        const int s = ss[0];
-        const int p = s / n_fine, m = s - p * n_fine;
-        r.f_best = sf[0];
-        r.period = 1.0 / r.f_best;
-        r.score = sq[0];
-        const double other = fine2 ? fine2[(int64_t)c * S + s] : NAN;
-        r.score_qmi = score_kind == 0 ? sq[0] : other;
-        r.score_nckp = score_kind == 0 ? other : sq[0];
-        r.coarse_index = po.peak_k[(int64_t)c * top_k + p];
-        r.peak_rank = p;
-        r.fine_index = m;
-    }
-    res[c] = r;
 }
 
 }  // namespace
@@ -891,24 +712,5 @@ template hipError_t launch_pairs<double>(hipStream_t, const CurveParams*, const 
                                          const FreqPlan&, const double*, const double*,
                                          const double*, const double*, const double*,
                                          const PairOut&, int);
-
-hipError_t launch_peaks(hipStream_t st, const CurveParams* cp, int n_curves, const double* coarse,
-                        int n_coarse, double f0, double df, int top_k, int n_fine,
-                        const PeakOut& po) {
-    if (n_curves <= 0) return hipSuccess;
-    peaks_kernel<<<n_curves, kPeakBlock, 0, st>>>(cp, coarse, n_coarse, f0, df, top_k, n_fine,
-                                                   po);
-    return hipGetLastError();
-}
-
-hipError_t launch_best(hipStream_t st, const CurveParams* cp, int n_curves, const double* coarse,
-                       const double* coarse2, int n_coarse, const double* fine,
-                       const double* fine2, int top_k, int n_fine, int score_kind, double f0,
-                       double df, const PeakOut& po, DevResult* res) {
-    if (n_curves <= 0) return hipSuccess;
-    best_kernel<<<n_curves, kBestBlock, 0, st>>>(cp, coarse, coarse2, n_coarse, fine, fine2, top_k,
-                                                  n_fine, score_kind, f0, df, po, res);
-    return hipGetLastError();
-}
 
 }  // namespace qmi

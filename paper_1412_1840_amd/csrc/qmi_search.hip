@@ -1,0 +1,235 @@
+// HIP kernels for gfx950 (MI355X): the search around the pair sums of Protopapas et al.,
+// arXiv:1412.1840 - the top local maxima of the coarse periodogram and their refinement windows
+// (the trial periods are kept at the highest maxima of a spectrum, Sec. 3.1), and the best
+// frequency of a curve (the score is maximised over trial frequencies, Sec. 3).
+#include <math.h>
+
+#include "qmi_internal.h"
+
+namespace qmi {
+
+namespace {
+
+// --------------------------------------------------------------------------------------------
+// Peaks: local maxima of the coarse scores, best top_k by (score desc, k asc), and their
+// refinement windows.  One block per curve.
+// --------------------------------------------------------------------------------------------
+
+constexpr int kPeakBlock = 256;
+
+__device__ __forceinline__ bool better(double qa, int ka, double qb, int kb) {
+    // a ranks before b: higher score, ties to lower index.  NaN never ranks.
+    if (!(qa == qa)) return false;
+    if (!(qb == qb)) return true;
+    return qa > qb || (qa == qb && ka < kb);
+}
+
+__device__ __forceinline__ double grid_f(double f0, double df, int k) {
+    return __dadd_rn(f0, __dmul_rn((double)k, df));
+}
+
+__global__ void __launch_bounds__(kPeakBlock)
+peaks_kernel(const CurveParams* __restrict__ cp, const double* __restrict__ coarse, int F,
+             double f0, double df, int top_k, int n_fine, PeakOut po) {
+    __shared__ double sq[kPeakBlock];
+    __shared__ int sk[kPeakBlock];
+    __shared__ int chosen[64];
+    extern __shared__ double peak_dyn[];  // [kPeakBlock][max(top_k, 1)] scores, then indices
+    const int c = blockIdx.x;
+    const double* q = coarse + (int64_t)c * F;
+    const bool ok = cp[c].status == 0;
+    // Coarse argmax (ties to lower k).
+    double bq = NAN;
+    int bk = 0x7fffffff;
+    if (ok)
+        for (int k = threadIdx.x; k < F; k += kPeakBlock)
+            if (better(q[k], k, bq, bk)) { bq = q[k]; bk = k; }
+    sq[threadIdx.x] = bq;
+    sk[threadIdx.x] = bk;
+    __syncthreads();
+    for (int s = kPeakBlock / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s && better(sq[threadIdx.x + s], sk[threadIdx.x + s], sq[threadIdx.x],
+                                      sk[threadIdx.x])) {
+            sq[threadIdx.x] = sq[threadIdx.x + s];
+            sk[threadIdx.x] = sk[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) po.argmax[c] = (sk[0] == 0x7fffffff) ? 0 : sk[0];
+    __syncthreads();
+    // The top_k local maxima: every thread keeps the best top_k of the maxima it scans, sorted
+    // (rank order: score descending, ties to the lower k), in its own LDS slots; then top_k rounds
+    // take the best head among the threads.  The result is the top_k of all maxima in rank order.
+    const int TK = top_k > 0 ? top_k : 1;
+    double* mv = reinterpret_cast<double*>(peak_dyn) + threadIdx.x * TK;
+    int* mk = reinterpret_cast<int*>(reinterpret_cast<double*>(peak_dyn) + kPeakBlock * TK) +
+              threadIdx.x * TK;
+    int n_loc = 0;
+    if (ok && top_k > 0) {
+        for (int k = threadIdx.x; k < F; k += kPeakBlock) {
+            const double v = q[k];
+            bool peak;
+            if (F == 1) peak = (v == v);
+            else if (k == 0) peak = v >= q[1];
+            else if (k == F - 1) peak = v > q[k - 1];
+            else peak = v > q[k - 1] && v >= q[k + 1];
+            if (!peak) continue;
+            if (n_loc == TK && !better(v, k, mv[TK - 1], mk[TK - 1])) continue;
+            int p = n_loc < TK ? n_loc++ : TK - 1;
+            while (p > 0 && better(v, k, mv[p - 1], mk[p - 1])) {
+                mv[p] = mv[p - 1];
+                mk[p] = mk[p - 1];
+                --p;
+            }
+            mv[p] = v;
+            mk[p] = k;
+        }
+    }
+    int count = 0, head = 0;
+    for (int p = 0; p < top_k && ok; ++p) {
+        bq = head < n_loc ? mv[head] : NAN;
+        bk = head < n_loc ? mk[head] : 0x7fffffff;
+        sq[threadIdx.x] = bq;
+        sk[threadIdx.x] = bk;
+        __syncthreads();
+        for (int s = kPeakBlock / 2; s > 0; s >>= 1) {
+            if (threadIdx.x < s && better(sq[threadIdx.x + s], sk[threadIdx.x + s],
+                                          sq[threadIdx.x], sk[threadIdx.x])) {
+                sq[threadIdx.x] = sq[threadIdx.x + s];
+                sk[threadIdx.x] = sk[threadIdx.x + s];
+            }
+            __syncthreads();
+        }
+        const int kk = sk[0];
+        __syncthreads();
+        if (kk == 0x7fffffff) break;
+        if (head < n_loc && mk[head] == kk) ++head;  // grid indices belong to one thread each
+        if (threadIdx.x == 0) chosen[count] = kk;
+        __syncthreads();
+        ++count;
+    }
+    if (threadIdx.x == 0) {
+        po.npk[c] = count;
+        for (int p = 0; p < count; ++p) {
+            const int k = chosen[p];
+            int a = k - 1, b = k + 1;
+            if (F == 1) { a = 0; b = 0; }
+            else if (k == 0) { a = 0; b = 1; }
+            else if (k == F - 1) { a = F - 2; b = F - 1; }
+            const double lo = grid_f(f0, df, a), hi = grid_f(f0, df, b);
+            po.peak_k[(int64_t)c * top_k + p] = k;
+            po.win[((int64_t)c * top_k + p) * 2 + 0] = lo;
+            po.win[((int64_t)c * top_k + p) * 2 + 1] = (hi - lo) / (double)(n_fine - 1);
+        }
+    }
+}
+
+// --------------------------------------------------------------------------------------------
+// Best-of: highest refined score, ties to the lower frequency then the lower peak rank.
+// --------------------------------------------------------------------------------------------
+
+constexpr int kBestBlock = 256;
+
+__global__ void __launch_bounds__(kBestBlock)
+best_kernel(const CurveParams* __restrict__ cp, const double* __restrict__ coarse,
+            const double* __restrict__ coarse2, int F,
+            const double* __restrict__ fine, const double* __restrict__ fine2, int top_k,
+            int n_fine, int score_kind, double f0, double df, PeakOut po,
+            DevResult* __restrict__ res) {
+    __shared__ double sq[kBestBlock], sf[kBestBlock];
+    __shared__ int ss[kBestBlock];
+    const int c = blockIdx.x;
+    const CurveParams P = cp[c];
+    const int npk = (top_k > 0 && n_fine > 0 && P.status == 0) ? po.npk[c] : 0;
+    const int64_t S = (int64_t)top_k * n_fine;
+    double bq = NAN, bf = INFINITY;
+    int bs = 0x7fffffff;
+    for (int s = threadIdx.x; s < npk * n_fine; s += kBestBlock) {
+        const double v = fine[(int64_t)c * S + s];
+        if (!(v == v)) continue;
+        const int p = s / n_fine, m = s - p * n_fine;
+        const double* w = po.win + ((int64_t)c * top_k + p) * 2;
+        const double fr = __dadd_rn(w[0], __dmul_rn((double)m, w[1]));
+        bool b = !(bq == bq) || v > bq || (v == bq && (fr < bf || (fr == bf && s < bs)));
+        if (b) { bq = v; bf = fr; bs = s; }
+    }
+    sq[threadIdx.x] = bq;
+    sf[threadIdx.x] = bf;
+    ss[threadIdx.x] = bs;
+    __syncthreads();
+    for (int h = kBestBlock / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            const double v = sq[threadIdx.x + h], fr = sf[threadIdx.x + h];
+            const int s = ss[threadIdx.x + h];
+            const double cq = sq[threadIdx.x], cf = sf[threadIdx.x];
+            const int cs = ss[threadIdx.x];
+            bool b = (v == v) &&
+                     (!(cq == cq) || v > cq || (v == cq && (fr < cf || (fr == cf && s < cs))));
+            if (b) { sq[threadIdx.x] = v; sf[threadIdx.x] = fr; ss[threadIdx.x] = s; }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    DevResult r;
+    r.sigma_y = P.sigma_y;
+    r.psnr = P.psnr;
+    r.n = P.n;
+    r.status = P.status;
+    r.reserved = 0;
+    r.n_peaks = npk;
+    const int am = (P.status == 0) ? po.argmax[c] : 0;
+    r.coarse_argmax = am;
+    r.coarse_best = (P.status == 0) ? coarse[(int64_t)c * F + am] : NAN;
+    if (P.status != 0) {
+        r.f_best = r.period = r.score = r.score_qmi = r.score_nckp = NAN;
+        r.coarse_index = r.peak_rank = r.fine_index = -1;
+    } else if (npk == 0 || ss[0] == 0x7fffffff) {
+        r.f_best = grid_f(f0, df, am);
+        r.period = 1.0 / r.f_best;
+        r.score = r.coarse_best;
+        r.coarse_index = am;
+        r.peak_rank = -1;
+        r.fine_index = -1;
+        const double other = coarse2 ? coarse2[(int64_t)c * F + am] : NAN;
+        r.score_qmi = score_kind == 0 ? r.coarse_best : other;
+        r.score_nckp = score_kind == 0 ? other : r.coarse_best;
+    } else {
+        const int s = ss[0];
+        const int p = s / n_fine, m = s - p * n_fine;
+        r.f_best = sf[0];
+        r.period = 1.0 / r.f_best;
+        r.score = sq[0];
+        const double other = fine2 ? fine2[(int64_t)c * S + s] : NAN;
+        r.score_qmi = score_kind == 0 ? sq[0] : other;
+        r.score_nckp = score_kind == 0 ? other : sq[0];
+        r.coarse_index = po.peak_k[(int64_t)c * top_k + p];
+        r.peak_rank = p;
+        r.fine_index = m;
+    }
+    res[c] = r;
+}
+
+}  // namespace
+
+hipError_t launch_peaks(hipStream_t st, const CurveParams* cp, int n_curves, const double* coarse,
+                        int n_coarse, double f0, double df, int top_k, int n_fine,
+                        const PeakOut& po) {
+    if (n_curves <= 0) return hipSuccess;
+    const size_t lds =
+        (size_t)kPeakBlock * (top_k > 0 ? top_k : 1) * (sizeof(double) + sizeof(int));
+    peaks_kernel<<<n_curves, kPeakBlock, lds, st>>>(cp, coarse, n_coarse, f0, df, top_k, n_fine,
+                                                     po);
+    return hipGetLastError();
+}
+
+hipError_t launch_best(hipStream_t st, const CurveParams* cp, int n_curves, const double* coarse,
+                       const double* coarse2, int n_coarse, const double* fine,
+                       const double* fine2, int top_k, int n_fine, int score_kind, double f0,
+                       double df, const PeakOut& po, DevResult* res) {
+    if (n_curves <= 0) return hipSuccess;
+    best_kernel<<<n_curves, kBestBlock, 0, st>>>(cp, coarse, coarse2, n_coarse, fine, fine2, top_k,
+                                                  n_fine, score_kind, f0, df, po, res);
+    return hipGetLastError();
+}
+
+}  // namespace qmi

@@ -149,7 +149,8 @@ int main(int argc, char** argv) {
     double ms_exp = time_ms([&] { exp_kernel<<<blocks, threads>>>(out, iters); });
     double ms_fma = time_ms([&] { fma_kernel<<<blocks, threads>>>(out, iters, 0.999f, 1e-3f); });
     const int reps = iters / 64 > 0 ? iters / 64 : 1;
-    double ms_pair = time_ms([&] { pair_kernel<<<blocks, threads>>>(out, cols, ncols, reps, 0.f); });
+    double ms_pair =
+        time_ms([&] { pair_kernel<<<blocks, threads>>>(out, cols, ncols, reps, 0.f); });
     const double exp_rate = lanes * iters * kChains / (ms_exp * 1e-3);
     const double fma_rate = lanes * iters * kChains / (ms_fma * 1e-3);
     const double pair_rate = lanes * (double)reps * ncols * 32 / (ms_pair * 1e-3);
