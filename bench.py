@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--cpu-freqs", type=int, default=4096,
                     help="coarse frequencies of the CPU-oracle sample (about 10 s on 16 cores)")
     ap.add_argument("--no-probe", action="store_true", help="skip the VALU rate probe")
-    ap.add_argument("--serve-requests", type=int, default=1000,
+    ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests of the serving measurement (0: skip)")
     ap.add_argument("--serve-load", type=float, default=0.5,
                     help="Poisson arrival rate as a fraction of the measured batch throughput")
@@ -50,11 +50,13 @@ def parse():
     ap.add_argument("--serve-sweep", default="",
                     help="comma-separated loads (fractions of the saturated serving throughput, "
                          "measured first); replaces --serve-load")
-    ap.add_argument("--serve-warmup", type=int, default=200,
+    ap.add_argument("--serve-warmup", type=int, default=500,
                     help="requests served first and left out of the latency statistics")
     ap.add_argument("--tile", type=int, default=0,
                     help="force pair-kernel variant k-1 (0: autotuned)")
     ap.add_argument("--no-graph-check", action="store_true")
+    ap.add_argument("--fp64-curves", type=int, default=256,
+                    help="curves of the all-FP64 path timing (0: skip)")
     ap.add_argument("--metric-point-steps", type=int, default=2,
                     help="timed steps of the same search with every curve at N = 600 (0: skip)")
     ap.add_argument("--bands-steps", type=int, default=2,
@@ -353,6 +355,24 @@ def main():
                         "roofline_frac_wall": mitems / mdt / PEAK_ITEMS_PER_S}
         del MT, MY, ME
 
+    # The all-FP64 path (QMI_PREC_FP64) on the first curves of the batch: the cost of full
+    # precision against the mixed path timed above.
+    fp64 = None
+    if a.fp64_curves > 0:
+        k64 = min(a.fp64_curves, nc)
+        o64 = batch.offsets[:k64 + 1]
+        s64 = int(o64[-1])
+        ctx.best_period_dev(o64, T[:s64], Y[:s64], E[:s64], st_, precision=qmi.PREC_FP64, **kw)
+        torch.cuda.synchronize()
+        d0 = time.perf_counter()
+        ctx.best_period_dev(o64, T[:s64], Y[:s64], E[:s64], st_, precision=qmi.PREC_FP64, **kw)
+        torch.cuda.synchronize()
+        d64 = time.perf_counter() - d0
+        i64 = ctx.stats()["pair_items"]
+        fp64 = {"curves": k64, "value": k64 / d64, "unit": "lightcurves/s",
+                "gpairs_per_s": i64 / d64 / 1e9,
+                "mixed_over_fp64": (items / (dt)) / (i64 / d64)}
+
     # Bands-method front end (Sec. 3.1: 3 bands x 150 trial frequencies instead of the coarse
     # grid and refinement) on the same batch, and the period recovery of both front ends against
     # the generator's truth: a periodic curve's period counts as recovered when the best frequency
@@ -457,6 +477,7 @@ def main():
         "graph": graph,
         "bands": bands,
         "metric_point": metric_point,
+        "fp64_path": fp64,
         "classification": classification,
         "plain": plain,
         "serving": serve,

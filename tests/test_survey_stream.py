@@ -114,3 +114,19 @@ def test_survey_runner_on_gpu_matches_one_call(tmp_path):
     with qmi.Context(0) as ctx:
         want, _ = ctx.best_period(b.offsets, b.t, b.y, b.e, 0.3, **SEARCH)
     assert got.tobytes() == want.tobytes()
+
+
+@pytest.mark.gpu
+def test_survey_command_line(tmp_path, capsys):
+    """python -m paper_1412_1840_amd.survey: the full survey-stream search on 40 curves in two
+    invocations (the second resumes), ending with a summary line."""
+    import json
+
+    from paper_1412_1840_amd import survey
+
+    out = str(tmp_path / "s")
+    assert survey.main(["--out", out, "--curves", "40", "--batch", "16", "--max-batches", "1"]) == 0
+    assert survey.main(["--out", out, "--curves", "40", "--batch", "16"]) == 0
+    summary = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    assert summary["curves_done"] == 40 and summary["batches"] == 3 and summary["bad_status"] == 0
+    assert summary["roofline_frac_kernel"] is not None
