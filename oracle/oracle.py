@@ -264,6 +264,47 @@ def fine_window(coarse: np.ndarray, k: int) -> Tuple[float, float]:
     return float(coarse[k - 1]), float(coarse[k + 1])
 
 
+# ------------------------------------------------------------------------------------------
+# Spurious-period filter (Sec. 6.1 and its table of spurious periods)
+# ------------------------------------------------------------------------------------------
+# Readings: a mask is a Gaussian in period, A exp(-(P - P_k)^2 / (2 sigma_k^2)), whose amplitude
+# A is in units of the searched score; a candidate (period P = 1/f, score s) falls inside it when
+# s < A exp(...), and a candidate inside any mask takes no part in the selection.  In the
+# coarse-to-fine search that means: the coarse argmax, the local maxima kept for refinement (the
+# local-maximum test itself still compares raw neighbours) and the best refined point are taken
+# over candidates outside every mask; in the bands method the best trial is.  With no candidate
+# left the result is empty (NaN).  The paper publishes the mask centres (its table) but not their
+# widths or amplitudes; the default width below is our own: half of one Fourier resolution
+# element 1/T of the survey span, mapped to period (sigma_k = 0.5 P_k^2 / T).
+
+SOLAR_DAY = 1.0
+SYNODIC_MONTH = 29.5305
+TROPICAL_YEAR = 365.24
+EROS_SPAN = 2335.0  # average time span of the survey's lightcurves (table of Sec. 6.1)
+
+# The table of Sec. 6.1, in its order: the four base periods, then their aliases as printed.
+SPURIOUS_PERIODS = (1.0, 29.5305, 365.24, 2335.0, 0.4917, 0.5086, 0.9672, 1.0351, 0.9973,
+                    1.0027, 27.31, 32.13, 315.65, 432.63)
+
+
+def spurious_masks(amplitude: float, span: float = EROS_SPAN,
+                   width: float = 0.5) -> List[Tuple[float, float, float]]:
+    """(P_k, sigma_k, A) for every period of the table, sigma_k = width P_k^2 / span."""
+    return [(p, width * p * p / span, float(amplitude)) for p in SPURIOUS_PERIODS]
+
+
+def in_mask(f: float, s: float, masks) -> bool:
+    """True when the candidate (1/f, s) lies under any mask (Sec. 6.1)."""
+    if not masks:
+        return False
+    P = 1.0 / f
+    for pk, sk, ak in masks:
+        d = P - pk
+        if s < ak * math.exp(-(d * d) / (2.0 * sk * sk)):
+            return True
+    return False
+
+
 @dataclass
 class SearchResult:
     f_best: float
@@ -283,7 +324,10 @@ class SearchResult:
 
 def best_period(t, y, e, sigma_t: float, sigma_y_rule: float, f_min: float, f_max: float,
                 n_coarse: int, top_k: int, n_fine: int, score: int = SCORE_QMI,
-                mode: int = 1, n_threads: int = 0) -> SearchResult:
+                mode: int = 1, n_threads: int = 0, masks=()) -> SearchResult:
+    """Coarse-to-fine search (Sec. 3, with the trial-selection rules listed at the top of this
+    module); candidates under a spurious-period mask (Sec. 6.1) are left out of every selection.
+    NaN scores never rank."""
     t = np.asarray(t, np.float64)
     y = np.asarray(y, np.float64)
     sy = sigma_y_of(y, None if e is None else np.asarray(e, np.float64), sigma_y_rule)
@@ -291,14 +335,27 @@ def best_period(t, y, e, sigma_t: float, sigma_y_rule: float, f_min: float, f_ma
     ips = information_potentials(t, y, sigma_t, sy, grid, mode, n_threads)
     q = score_of(ips, score)
     q_all = (qmi(ips), nckp(ips))
-    arg = int(np.argmax(q)) if not np.all(np.isnan(q)) else 0  # np.argmax: first maximum
+
+    def usable(f, v):
+        return v == v and not in_mask(f, v, masks)
+
+    cand = [k for k in range(n_coarse) if usable(grid[k], q[k])]
+    arg = min(cand, key=lambda k: (-q[k], k)) if cand else -1
+
+    def coarse_result(n_peaks, fq):
+        if arg < 0:
+            return SearchResult(math.nan, math.nan, math.nan, math.nan, -1, -1, -1, -1, n_peaks,
+                                sy, ips.ipy, q, fq)
+        return SearchResult(float(grid[arg]), float(q[arg]), float(q_all[0][arg]),
+                            float(q_all[1][arg]), arg, -1, -1, arg, n_peaks, sy, ips.ipy, q, fq)
+
     if top_k <= 0 or n_fine <= 0:
-        return SearchResult(float(grid[arg]), float(q[arg]), float(q_all[0][arg]),
-                            float(q_all[1][arg]), arg, -1, -1, arg, 0, sy, ips.ipy, q, None)
-    peaks = top_peaks(q, top_k)
+        return coarse_result(0, None)
+    peaks = [k for k in local_maxima(q) if usable(grid[k], q[k])]
+    peaks.sort(key=lambda k: (-q[k], k))
+    peaks = peaks[:top_k]
     if not peaks:
-        return SearchResult(float(grid[arg]), float(q[arg]), float(q_all[0][arg]),
-                            float(q_all[1][arg]), arg, -1, -1, arg, 0, sy, ips.ipy, q, None)
+        return coarse_result(0, None)
     fine_f = [linear_grid(*fine_window(grid, k), n_fine) for k in peaks]
     fips = information_potentials(t, y, sigma_t, sy, np.concatenate(fine_f), mode, n_threads)
     fq = score_of(fips, score).reshape(len(peaks), n_fine)
@@ -306,14 +363,13 @@ def best_period(t, y, e, sigma_t: float, sigma_y_rule: float, f_min: float, f_ma
     best = None
     for rank, k in enumerate(peaks):
         for m in range(n_fine):
-            key = (-fq[rank, m], fine_f[rank][m], rank, m)
-            if not (fq[rank, m] == fq[rank, m]):
+            if not usable(fine_f[rank][m], fq[rank, m]):
                 continue
+            key = (-fq[rank, m], fine_f[rank][m], rank, m)
             if best is None or key < best[0]:
                 best = (key, rank, m)
     if best is None:
-        return SearchResult(float(grid[arg]), float(q[arg]), float(q_all[0][arg]),
-                            float(q_all[1][arg]), arg, -1, -1, arg, len(peaks), sy, ips.ipy, q, fq)
+        return coarse_result(len(peaks), fq)
     _, rank, m = best
     return SearchResult(float(fine_f[rank][m]), float(fq[rank, m]), float(fq_all[0][rank, m]),
                         float(fq_all[1][rank, m]), peaks[rank], rank, m, arg, len(peaks), sy,
@@ -466,8 +522,9 @@ def bands_trial_frequencies(t, y, n_keep: int = 3, n_trials: int = 150,
 
 def bands_best_period(t, y, e, sigma_t: float, sigma_y_rule: float, n_keep: int = 3,
                       n_trials: int = 150, score: int = SCORE_QMI, n_grid: int = BANDS_GRID,
-                      n_threads: int = 0) -> Dict[str, object]:
-    """The score at every trial frequency and the best trial (Sec. 3.1 followed by Sec. 3)."""
+                      n_threads: int = 0, masks=()) -> Dict[str, object]:
+    """The score at every trial frequency and the best trial (Sec. 3.1 followed by Sec. 3),
+    leaving out trials under a spurious-period mask (Sec. 6.1)."""
     tr = bands_trial_frequencies(t, y, n_keep, n_trials, n_grid=n_grid)
     f = tr["freqs"]
     sy = sigma_y_of(np.asarray(y, np.float64), None if e is None else np.asarray(e, np.float64),
@@ -478,7 +535,7 @@ def bands_best_period(t, y, e, sigma_t: float, sigma_y_rule: float, n_keep: int 
     q = score_of(ips, score)
     best = None
     for i in range(len(f)):
-        if not (q[i] == q[i]):
+        if not (q[i] == q[i]) or in_mask(f[i], q[i], masks):
             continue
         key = (-q[i], f[i], i)
         if best is None or key < best:
