@@ -57,6 +57,7 @@ extern "C" {
 #define QMI_MAX_TOPK 32 /* refined peaks per curve */
 #define QMI_MAX_BANDS 32    /* magnitude bands of the bands method */
 #define QMI_MAX_TRIALS 1024 /* trial frequencies per band of the bands method */
+#define QMI_MAX_MASKS 32     /* spurious-period masks (qmi_set_masks) */
 
 /* sigma_y rules (qmi_kernel_params.sigma_y <= 0 selects a rule). */
 #define QMI_SIGMA_SILVERMAN (-1.0)  /* 0.9 min(s, IQR/1.34) N^(-1/5); s on N-1, linear quartiles */
@@ -112,6 +113,7 @@ typedef struct {
  * are each refined on n_fine evenly spaced points of [f_{k-1}, f_{k+1}] ([f_0, f_1], [f_{F-2},
  * f_{F-1}] at the ends).  The best is the highest refined score, ties to the lower frequency, then
  * to the lower peak rank.  top_k = 0 (or n_fine = 0) returns the coarse argmax (ties to lower k).
+ * Masks set with qmi_set_masks leave their candidates out of each of these selections.
  * Requirements: 0 <= f_min < f_max, 1 <= n_coarse <= 2^26, 0 <= top_k <= QMI_MAX_TOPK,
  * n_fine == 0 or 2 <= n_fine <= 2^20, score one of QMI_SCORE_*.
  */
@@ -143,6 +145,20 @@ typedef struct {
     int32_t reserved;
 } qmi_bands;
 
+/*
+ * One spurious-period mask (Sec. 6.1): a Gaussian in period, amplitude * exp(-(P - period)^2 /
+ * (2 sigma^2)), with the amplitude in units of the searched score.  A candidate frequency f with
+ * score s lies inside it when s < amplitude * exp(-(1/f - period)^2 / (2 sigma^2)).  The paper
+ * centres masks on the periods of its table of spurious periods (the solar day, the synodic month,
+ * the tropical year, the survey's mean span and their aliases) and tunes widths and amplitudes
+ * on the survey's period histogram; it does not publish them.
+ */
+typedef struct {
+    double period;    /* days, > 0 */
+    double sigma;     /* days, > 0 */
+    double amplitude; /* score units, finite */
+} qmi_mask;
+
 /* Per-curve result of qmi_best_period (and of qmi_bands_best_period, which uses the integer
  * fields as noted in its description). */
 typedef struct {
@@ -157,7 +173,7 @@ typedef struct {
     int32_t coarse_index;  /* k of the refined peak holding f_best (coarse_argmax without refinement) */
     int32_t peak_rank;     /* its rank among the refined peaks (-1 without refinement) */
     int32_t fine_index;    /* index of f_best inside that peak's fine grid (-1 without refinement) */
-    int32_t coarse_argmax; /* plain argmax of the coarse scores */
+    int32_t coarse_argmax; /* argmax of the coarse scores outside every mask (-1: none) */
     int32_t n_peaks;       /* number of refined peaks */
     int32_t n;             /* samples */
     int32_t status;        /* QMI_OK or the per-curve QMI_E* code */
@@ -207,6 +223,20 @@ int qmi_set_option(qmi_ctx *ctx, int32_t option, int64_t value);
 
 /* Copy the timing of the last call into *out. */
 int qmi_get_stats(const qmi_ctx *ctx, qmi_stats *out);
+
+/*
+ * Spurious-period filter (Sec. 6.1) for the searches that follow on this context: qmi_best_period
+ * (and _dev), qmi_bands_best_period and serving started afterwards.  Candidates inside any mask
+ * take no part in a selection: the coarse argmax, the local maxima kept for refinement (the
+ * local-maximum test still compares raw neighbours), the best refined point, and the best trial of
+ * the bands method are each taken over candidates outside every mask.  A curve with no candidate
+ * left gets f_best = period = score = NaN and coarse_index = coarse_argmax = -1 (status stays
+ * QMI_OK).  Periodograms are not masked.
+ *   masks    host, [n_masks], copied; NULL with n_masks = 0 removes every mask (the default)
+ * QMI_EINVAL when n_masks < 0 or > QMI_MAX_MASKS, masks is NULL with n_masks > 0, a period or sigma
+ * is not finite and positive, an amplitude is not finite, or serving is running on ctx.
+ */
+int qmi_set_masks(qmi_ctx *ctx, const qmi_mask *masks, int32_t n_masks);
 
 /*
  * Periodogram at a caller-supplied frequency list (the same list for every curve).

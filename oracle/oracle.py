@@ -320,6 +320,7 @@ class SearchResult:
     ipy: float
     coarse_scores: np.ndarray
     fine_scores: Optional[np.ndarray]  # [n_peaks, n_fine]
+    peaks: Optional[List[int]] = None  # the refined peaks' k, in rank order
 
 
 def best_period(t, y, e, sigma_t: float, sigma_y_rule: float, f_min: float, f_max: float,
@@ -342,12 +343,13 @@ def best_period(t, y, e, sigma_t: float, sigma_y_rule: float, f_min: float, f_ma
     cand = [k for k in range(n_coarse) if usable(grid[k], q[k])]
     arg = min(cand, key=lambda k: (-q[k], k)) if cand else -1
 
-    def coarse_result(n_peaks, fq):
+    def coarse_result(n_peaks, fq, peaks=None):
         if arg < 0:
             return SearchResult(math.nan, math.nan, math.nan, math.nan, -1, -1, -1, -1, n_peaks,
-                                sy, ips.ipy, q, fq)
+                                sy, ips.ipy, q, fq, peaks)
         return SearchResult(float(grid[arg]), float(q[arg]), float(q_all[0][arg]),
-                            float(q_all[1][arg]), arg, -1, -1, arg, n_peaks, sy, ips.ipy, q, fq)
+                            float(q_all[1][arg]), arg, -1, -1, arg, n_peaks, sy, ips.ipy, q, fq,
+                            peaks)
 
     if top_k <= 0 or n_fine <= 0:
         return coarse_result(0, None)
@@ -369,11 +371,11 @@ def best_period(t, y, e, sigma_t: float, sigma_y_rule: float, f_min: float, f_ma
             if best is None or key < best[0]:
                 best = (key, rank, m)
     if best is None:
-        return coarse_result(len(peaks), fq)
+        return coarse_result(len(peaks), fq, peaks)
     _, rank, m = best
     return SearchResult(float(fine_f[rank][m]), float(fq[rank, m]), float(fq_all[0][rank, m]),
                         float(fq_all[1][rank, m]), peaks[rank], rank, m, arg, len(peaks), sy,
-                        ips.ipy, q, fq)
+                        ips.ipy, q, fq, peaks)
 
 
 # ------------------------------------------------------------------------------------------

@@ -67,6 +67,8 @@ struct qmi_ctx {
     std::vector<uint64_t> graph_key;
     // Autotuner: pair-kernel variant per length bucket (-1: not tuned yet).
     int tuned[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+    // Spurious-period masks applied by the selection kernels (qmi_set_masks).
+    qmi::MaskDev masks{};
     // Serving.
     struct Serve;
     std::unique_ptr<Serve> serve;
@@ -580,11 +582,12 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
         HIP_OK(ctx, launch_pairs<R>(st, dcp, dorder, nc, fp, t, K, rd, rp, ks, po, variant));
         rec();
         if (bp) {
-            HIP_OK(ctx, launch_bands_best(st, dcp, nc, coarse, coarse2, score_kind, bd, dres));
+            HIP_OK(ctx, launch_bands_best(st, dcp, nc, coarse, coarse2, score_kind, bd,
+                                          ctx->masks, dres));
         } else if (!cs.periodogram) {
             const qmi_search* s = cs.search;
             HIP_OK(ctx, launch_peaks(st, dcp, nc, coarse, s->n_coarse, fp.f0, fp.df, top_k,
-                                     std::max(n_fine, 2), pk));
+                                     std::max(n_fine, 2), ctx->masks, pk));
             if (refine) {
                 PairOut fo{fine, fine2, nullptr, score_kind, 0};
                 if (events) pair_event_idx.push_back(ctx->ev_used);
@@ -595,7 +598,7 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
             }
             HIP_OK(ctx, launch_best(st, dcp, nc, coarse, coarse2, s->n_coarse, fine, fine2,
                                     refine ? top_k : 0, refine ? n_fine : 0, score_kind, fp.f0,
-                                    fp.df, pk, dres));
+                                    fp.df, ctx->masks, pk, dres));
         }
         rec();  // device section end
         return QMI_OK;
@@ -1053,6 +1056,36 @@ int qmi_get_stats(const qmi_ctx* ctx, qmi_stats* out) {
     return QMI_OK;
 }
 
+int qmi_set_masks(qmi_ctx* ctx, const qmi_mask* masks, int32_t n_masks) {
+    if (!ctx) return QMI_EINVAL;
+    if (n_masks < 0 || n_masks > QMI_MAX_MASKS || (n_masks > 0 && !masks)) {
+        set_err(ctx, "qmi_set_masks: need 0 <= n_masks <= %d and a table", QMI_MAX_MASKS);
+        return QMI_EINVAL;
+    }
+    if (ctx->serve) {
+        set_err(ctx, "qmi_set_masks: serving is running");
+        return QMI_EINVAL;
+    }
+    qmi::MaskDev md{};
+    for (int i = 0; i < n_masks; ++i) {
+        const qmi_mask& m = masks[i];
+        if (!(std::isfinite(m.period) && m.period > 0.0 && std::isfinite(m.sigma) &&
+              m.sigma > 0.0 && std::isfinite(m.amplitude))) {
+            set_err(ctx, "qmi_set_masks: mask %d needs a finite positive period and sigma and a "
+                    "finite amplitude", i);
+            return QMI_EINVAL;
+        }
+        md.period[i] = m.period;
+        md.sigma[i] = m.sigma;
+        md.amp[i] = m.amplitude;
+    }
+    md.n = n_masks;
+    // A captured graph holds the previous table in its kernel arguments.
+    drop_graph(ctx);
+    ctx->masks = md;
+    return QMI_OK;
+}
+
 int qmi_periodogram(qmi_ctx* ctx, const qmi_batch* batch, const qmi_kernel_params* kp,
                     const double* freqs, int32_t n_freq, int32_t score, double* score_out,
                     double* ips_out, double* ip_y_out, int32_t* status_out) {
@@ -1467,6 +1500,7 @@ int qmi_serve_start(qmi_ctx* ctx, const qmi_kernel_params* kp, const qmi_search*
         // Serving batches differ in composition, so a captured graph would almost never be
         // replayed: the lanes launch eagerly.
         lc->use_graph = false;
+        lc->masks = ctx->masks;
         S->lanes.push_back(lc);
     }
     ctx->serve = std::move(S);

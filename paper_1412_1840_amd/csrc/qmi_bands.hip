@@ -358,7 +358,8 @@ trials_kernel(const CurveParams* __restrict__ cp, BandsDev bd) {
     }
 }
 
-// Best trial per curve: highest score, ties to the lower frequency, then the earlier trial.
+// Best trial per curve: highest score outside every spurious-period mask (Sec. 6.1), ties to the
+// lower frequency, then the earlier trial.
 constexpr int kBandsBestBlock = 256;
 
 __device__ __forceinline__ bool trial_before(double qa, double fa, int sa, double qb, double fb,
@@ -372,7 +373,7 @@ __device__ __forceinline__ bool trial_before(double qa, double fa, int sa, doubl
 
 __global__ void __launch_bounds__(kBandsBestBlock)
 bands_best_kernel(const CurveParams* __restrict__ cp, const double* __restrict__ score,
-                  const double* __restrict__ score2, int score_kind, BandsDev bd,
+                  const double* __restrict__ score2, int score_kind, BandsDev bd, MaskDev md,
                   DevResult* __restrict__ res) {
     __shared__ double sq[kBandsBestBlock], sf[kBandsBestBlock];
     __shared__ int ss[kBandsBestBlock], sfound[kBandsBestBlock];
@@ -388,7 +389,7 @@ bands_best_kernel(const CurveParams* __restrict__ cp, const double* __restrict__
             const double f = fr[s];
             if (!(f == f)) continue;
             ++found;
-            if (trial_before(q[s], f, s, bq, bf, bs)) {
+            if (trial_before(q[s], f, s, bq, bf, bs) && !in_mask(md, f, q[s])) {
                 bq = q[s];
                 bf = f;
                 bs = s;
@@ -468,10 +469,10 @@ hipError_t launch_bands(hipStream_t st, const CurveParams* cp, int n_curves, int
 
 hipError_t launch_bands_best(hipStream_t st, const CurveParams* cp, int n_curves,
                              const double* score, const double* score2, int score_kind,
-                             const BandsDev& bd, DevResult* res) {
+                             const BandsDev& bd, const MaskDev& md, DevResult* res) {
     if (n_curves <= 0) return hipSuccess;
     bands_best_kernel<<<n_curves, kBandsBestBlock, 0, st>>>(cp, score, score2, score_kind, bd,
-                                                             res);
+                                                             md, res);
     return hipGetLastError();
 }
 

@@ -90,6 +90,26 @@ struct PeakOut {
     int32_t* argmax;   // [curve]
 };
 
+// Spurious-period masks (Sec. 6.1), passed to the selection kernels by value.  A candidate (f, s)
+// is inside mask i when s < amp[i] exp(-(1/f - period[i])^2 / (2 sigma[i]^2)).
+struct MaskDev {
+    int32_t n;
+    int32_t pad;
+    double period[QMI_MAX_MASKS];
+    double sigma[QMI_MAX_MASKS];
+    double amp[QMI_MAX_MASKS];
+};
+
+__device__ __forceinline__ bool in_mask(const MaskDev& md, double f, double s) {
+    if (md.n == 0) return false;
+    const double P = 1.0 / f;
+    for (int i = 0; i < md.n; ++i) {
+        const double d = P - md.period[i];
+        if (s < md.amp[i] * exp(-(d * d) / (2.0 * md.sigma[i] * md.sigma[i]))) return true;
+    }
+    return false;
+}
+
 // Result record written by the best-of kernel (mirrors qmi_result field order).
 struct DevResult {
     double f_best, period, score, score_qmi, score_nckp, sigma_y, psnr, coarse_best;
@@ -116,7 +136,7 @@ hipError_t launch_bands(hipStream_t st, const CurveParams* cp, int n_curves, int
                         const double* t, const double* y, const BandsDev& bd);
 hipError_t launch_bands_best(hipStream_t st, const CurveParams* cp, int n_curves,
                              const double* score, const double* score2, int score_kind,
-                             const BandsDev& bd, DevResult* res);
+                             const BandsDev& bd, const MaskDev& md, DevResult* res);
 
 // Preprocessing and whitening (qmi_prep.hip).
 struct PrepDev {
@@ -160,10 +180,10 @@ hipError_t launch_pairs(hipStream_t st, const CurveParams* cp, const int32_t* or
                         int variant);
 hipError_t launch_peaks(hipStream_t st, const CurveParams* cp, int n_curves, const double* coarse,
                         int n_coarse, double f0, double df, int top_k, int n_fine,
-                        const PeakOut& po);
+                        const MaskDev& md, const PeakOut& po);
 hipError_t launch_best(hipStream_t st, const CurveParams* cp, int n_curves, const double* coarse,
                        const double* coarse2, int n_coarse, const double* fine,
                        const double* fine2, int top_k, int n_fine, int score_kind, double f0,
-                       double df, const PeakOut& po, DevResult* res);
+                       double df, const MaskDev& md, const PeakOut& po, DevResult* res);
 
 }  // namespace qmi

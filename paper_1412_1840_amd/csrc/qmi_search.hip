@@ -12,7 +12,8 @@ namespace {
 
 // --------------------------------------------------------------------------------------------
 // Peaks: local maxima of the coarse scores, best top_k by (score desc, k asc), and their
-// refinement windows.  One block per curve.
+// refinement windows.  Candidates inside a spurious-period mask (Sec. 6.1) are left out of the
+// argmax and of the maxima kept.  One block per curve.
 // --------------------------------------------------------------------------------------------
 
 constexpr int kPeakBlock = 256;
@@ -30,7 +31,7 @@ __device__ __forceinline__ double grid_f(double f0, double df, int k) {
 
 __global__ void __launch_bounds__(kPeakBlock)
 peaks_kernel(const CurveParams* __restrict__ cp, const double* __restrict__ coarse, int F,
-             double f0, double df, int top_k, int n_fine, PeakOut po) {
+             double f0, double df, int top_k, int n_fine, MaskDev md, PeakOut po) {
     __shared__ double sq[kPeakBlock];
     __shared__ int sk[kPeakBlock];
     __shared__ int chosen[64];
@@ -38,12 +39,15 @@ peaks_kernel(const CurveParams* __restrict__ cp, const double* __restrict__ coar
     const int c = blockIdx.x;
     const double* q = coarse + (int64_t)c * F;
     const bool ok = cp[c].status == 0;
-    // Coarse argmax (ties to lower k).
+    // Coarse argmax (ties to lower k) over the candidates outside every mask.
     double bq = NAN;
     int bk = 0x7fffffff;
     if (ok)
         for (int k = threadIdx.x; k < F; k += kPeakBlock)
-            if (better(q[k], k, bq, bk)) { bq = q[k]; bk = k; }
+            if (better(q[k], k, bq, bk) && !in_mask(md, grid_f(f0, df, k), q[k])) {
+                bq = q[k];
+                bk = k;
+            }
     sq[threadIdx.x] = bq;
     sk[threadIdx.x] = bk;
     __syncthreads();
@@ -55,7 +59,7 @@ peaks_kernel(const CurveParams* __restrict__ cp, const double* __restrict__ coar
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) po.argmax[c] = (sk[0] == 0x7fffffff) ? 0 : sk[0];
+    if (threadIdx.x == 0) po.argmax[c] = (sk[0] == 0x7fffffff) ? -1 : sk[0];
     __syncthreads();
     // The top_k local maxima: every thread keeps the best top_k of the maxima it scans, sorted
     // (rank order: score descending, ties to the lower k), in its own LDS slots; then top_k rounds
@@ -75,6 +79,7 @@ peaks_kernel(const CurveParams* __restrict__ cp, const double* __restrict__ coar
             else peak = v > q[k - 1] && v >= q[k + 1];
             if (!peak) continue;
             if (n_loc == TK && !better(v, k, mv[TK - 1], mk[TK - 1])) continue;
+            if (in_mask(md, grid_f(f0, df, k), v)) continue;
             int p = n_loc < TK ? n_loc++ : TK - 1;
             while (p > 0 && better(v, k, mv[p - 1], mk[p - 1])) {
                 mv[p] = mv[p - 1];
@@ -125,7 +130,8 @@ peaks_kernel(const CurveParams* __restrict__ cp, const double* __restrict__ coar
 }
 
 // --------------------------------------------------------------------------------------------
-// Best-of: highest refined score, ties to the lower frequency then the lower peak rank.
+// Best-of: highest refined score outside every mask, ties to the lower frequency then the lower
+// peak rank; without a refined candidate, the coarse argmax; without that, an empty result.
 // --------------------------------------------------------------------------------------------
 
 constexpr int kBestBlock = 256;
@@ -134,7 +140,7 @@ __global__ void __launch_bounds__(kBestBlock)
 best_kernel(const CurveParams* __restrict__ cp, const double* __restrict__ coarse,
             const double* __restrict__ coarse2, int F,
             const double* __restrict__ fine, const double* __restrict__ fine2, int top_k,
-            int n_fine, int score_kind, double f0, double df, PeakOut po,
+            int n_fine, int score_kind, double f0, double df, MaskDev md, PeakOut po,
             DevResult* __restrict__ res) {
     __shared__ double sq[kBestBlock], sf[kBestBlock];
     __shared__ int ss[kBestBlock];
@@ -151,7 +157,7 @@ best_kernel(const CurveParams* __restrict__ cp, const double* __restrict__ coars
         const double* w = po.win + ((int64_t)c * top_k + p) * 2;
         const double fr = __dadd_rn(w[0], __dmul_rn((double)m, w[1]));
         bool b = !(bq == bq) || v > bq || (v == bq && (fr < bf || (fr == bf && s < bs)));
-        if (b) { bq = v; bf = fr; bs = s; }
+        if (b && !in_mask(md, fr, v)) { bq = v; bf = fr; bs = s; }
     }
     sq[threadIdx.x] = bq;
     sf[threadIdx.x] = bf;
@@ -177,10 +183,10 @@ best_kernel(const CurveParams* __restrict__ cp, const double* __restrict__ coars
     r.status = P.status;
     r.reserved = 0;
     r.n_peaks = npk;
-    const int am = (P.status == 0) ? po.argmax[c] : 0;
+    const int am = (P.status == 0) ? po.argmax[c] : -1;
     r.coarse_argmax = am;
-    r.coarse_best = (P.status == 0) ? coarse[(int64_t)c * F + am] : NAN;
-    if (P.status != 0) {
+    r.coarse_best = (am >= 0) ? coarse[(int64_t)c * F + am] : NAN;
+    if (P.status != 0 || ((npk == 0 || ss[0] == 0x7fffffff) && am < 0)) {
         r.f_best = r.period = r.score = r.score_qmi = r.score_nckp = NAN;
         r.coarse_index = r.peak_rank = r.fine_index = -1;
     } else if (npk == 0 || ss[0] == 0x7fffffff) {
@@ -213,22 +219,22 @@ best_kernel(const CurveParams* __restrict__ cp, const double* __restrict__ coars
 
 hipError_t launch_peaks(hipStream_t st, const CurveParams* cp, int n_curves, const double* coarse,
                         int n_coarse, double f0, double df, int top_k, int n_fine,
-                        const PeakOut& po) {
+                        const MaskDev& md, const PeakOut& po) {
     if (n_curves <= 0) return hipSuccess;
     const size_t lds =
         (size_t)kPeakBlock * (top_k > 0 ? top_k : 1) * (sizeof(double) + sizeof(int));
     peaks_kernel<<<n_curves, kPeakBlock, lds, st>>>(cp, coarse, n_coarse, f0, df, top_k, n_fine,
-                                                     po);
+                                                     md, po);
     return hipGetLastError();
 }
 
 hipError_t launch_best(hipStream_t st, const CurveParams* cp, int n_curves, const double* coarse,
                        const double* coarse2, int n_coarse, const double* fine,
                        const double* fine2, int top_k, int n_fine, int score_kind, double f0,
-                       double df, const PeakOut& po, DevResult* res) {
+                       double df, const MaskDev& md, const PeakOut& po, DevResult* res) {
     if (n_curves <= 0) return hipSuccess;
     best_kernel<<<n_curves, kBestBlock, 0, st>>>(cp, coarse, coarse2, n_coarse, fine, fine2, top_k,
-                                                  n_fine, score_kind, f0, df, po, res);
+                                                  n_fine, score_kind, f0, df, md, po, res);
     return hipGetLastError();
 }
 

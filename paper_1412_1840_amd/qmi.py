@@ -38,11 +38,13 @@ MAX_N = 8192
 MAX_TOPK = 32
 MAX_BANDS = 32
 MAX_TRIALS = 1024
+MAX_MASKS = 32
 
 SYMBOLS = ("qmi_create", "qmi_destroy", "qmi_last_error", "qmi_set_option", "qmi_get_stats",
            "qmi_periodogram", "qmi_best_period", "qmi_periodogram_dev", "qmi_best_period_dev",
            "qmi_discriminate", "qmi_calibrate", "qmi_serve_start", "qmi_submit", "qmi_poll",
-           "qmi_serve_stop", "qmi_bands_best_period", "qmi_preprocess", "qmi_whiten")
+           "qmi_serve_stop", "qmi_bands_best_period", "qmi_preprocess", "qmi_whiten",
+           "qmi_set_masks")
 SNR_EDGES = (0.0, 1.5, 2.0, 2.5, 3.5, 5.0, 10.0, 20.0, math.inf)
 
 
@@ -78,6 +80,24 @@ class Bands(ctypes.Structure):
 class PreprocessParams(ctypes.Structure):
     _fields_ = [("error_cut", ctypes.c_int32), ("min_samples", ctypes.c_int32),
                 ("detrend", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Mask(ctypes.Structure):
+    _fields_ = [("period", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("amplitude", ctypes.c_double)]
+
+
+# Centres of the spurious-period masks of Sec. 6.1 (days), in the order of the paper's table: the
+# solar day, the synodic month, the tropical year, the survey's mean span, then their aliases.
+SPURIOUS_PERIODS = (1.0, 29.5305, 365.24, 2335.0, 0.4917, 0.5086, 0.9672, 1.0351, 0.9973,
+                    1.0027, 27.31, 32.13, 315.65, 432.63)
+
+
+def spurious_masks(amplitude: float, span: float = 2335.0, width: float = 0.5):
+    """(period, sigma, amplitude) for every period of the table of Sec. 6.1.  The paper does not
+    publish its widths and amplitudes; sigma = width * P^2 / span is `width` Fourier resolution
+    elements 1/span mapped to period, and the amplitude is in units of the searched score."""
+    return [(p, width * p * p / span, float(amplitude)) for p in SPURIOUS_PERIODS]
 
 
 class Thresholds(ctypes.Structure):
@@ -126,6 +146,8 @@ def lib() -> ctypes.CDLL:
         L.qmi_last_error.restype = ctypes.c_char_p
         L.qmi_set_option.argtypes = [V, I32, I64]
         L.qmi_get_stats.argtypes = [V, P(Stats)]
+        L.qmi_set_masks.argtypes = [V, V, I32]
+        L.qmi_set_masks.restype = ctypes.c_int
         for name in ("qmi_periodogram", "qmi_periodogram_dev"):
             f = getattr(L, name)
             f.argtypes = [V, P(Batch), P(KernelParams), V, I32, I32, V, V, V, V]
@@ -243,6 +265,14 @@ class Context:
 
     def set_option(self, option: int, value: int):
         self._check(lib().qmi_set_option(self._h, int(option), int(value)))
+
+    def set_masks(self, masks=None):
+        """Spurious-period masks [(period, sigma, amplitude), ...] for the searches that follow
+        (None or [] removes them)."""
+        masks = list(masks or [])
+        arr = (Mask * max(len(masks), 1))(*[Mask(*map(float, m)) for m in masks])
+        self._check(lib().qmi_set_masks(self._h, ctypes.addressof(arr) if masks else None,
+                                        len(masks)))
 
     def stats(self) -> dict:
         s = Stats()

@@ -45,6 +45,7 @@ def test_header_constants_match_binding():
     assert val("QMI_MAX_N") == qmi.MAX_N and val("QMI_MAX_TOPK") == qmi.MAX_TOPK
     assert val("QMI_UNDECIDED") == qmi.UNDECIDED
     assert val("QMI_MAX_BANDS") == qmi.MAX_BANDS and val("QMI_MAX_TRIALS") == qmi.MAX_TRIALS
+    assert val("QMI_MAX_MASKS") == qmi.MAX_MASKS
     assert val("QMI_PREC_FOLD32") == qmi.PREC_FOLD32
 
 
@@ -56,6 +57,7 @@ def test_struct_sizes():
     assert ctypes.sizeof(qmi.Thresholds) == 24
     assert ctypes.sizeof(qmi.Bands) == 40
     assert ctypes.sizeof(qmi.PreprocessParams) == 16
+    assert ctypes.sizeof(qmi.Mask) == 24
     assert qmi.RESULT_DTYPE.itemsize == 96
 
 
@@ -120,3 +122,11 @@ def test_calibration_matches_oracle():
     # empty bins and bins without periodic members
     got = qmi.calibrate([0.5, 0.7], [1.0, 1.2], [0, 0])
     assert got["th"][0] == 0.7 and got["f1"][0] == 0.0 and np.isinf(got["th"][1])
+
+
+def test_spurious_table_of_the_binding_is_the_papers():
+    """The binding's copy of the table of spurious periods (Sec. 6.1) and its default mask widths
+    agree with the oracle's transcription."""
+    assert qmi.SPURIOUS_PERIODS == O.SPURIOUS_PERIODS
+    for amp, w in ((0.7, 0.5), (2.0, 20.0)):
+        assert qmi.spurious_masks(amp, width=w) == O.spurious_masks(amp, width=w)

@@ -1,0 +1,191 @@
+"""Parity of the spurious-period filter (qmi_set_masks, Sec. 6.1) with the FP64 oracle.
+
+A mask decision compares a score with a Gaussian of the period; the GPU takes it on its own
+(mixed-precision) score, the oracle on its FP64 score.  Curves where any candidate of the oracle's
+search lies within 2e-4 (relative, with the floor of the QMI bar) of a mask's edge are not compared
+(a near-boundary decision may go either way); the inputs make these rare.  Elsewhere the selected
+candidates must be identical, or, where the oracle's best is a flat maximum, the GPU's choice must
+be outside every mask and score within 1e-5 of the oracle's best under the oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1412_1840_amd import qmi, synth
+
+pytestmark = pytest.mark.gpu
+
+QMI_TOL = 1e-4
+KW = dict(f_min=1e-3, f_max=10.0, n_coarse=3000, top_k=5, n_fine=64)
+NS = [140, 260, 390, 120, 333, 201, 288, 175, 360, 150, 240, 310]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    with qmi.Context(0) as c:
+        yield c
+
+
+def _curves():
+    return [synth.survey_batch_curve(k, n=n) for k, n in enumerate(NS)]
+
+
+def _margin(f, s, masks, floor):
+    """Smallest relative distance of (f, s) from any mask's edge."""
+    P = 1.0 / f
+    worst = math.inf
+    for pk, sk, ak in masks:
+        m = ak * math.exp(-((P - pk) ** 2) / (2.0 * sk * sk))
+        worst = min(worst, abs(s - m) / max(abs(s), floor))
+    return worst
+
+
+def _near_edge(o, masks, grid):
+    floor = 1e-3 * float(np.nanmax(np.abs(o.coarse_scores)))
+    for f, s in zip(grid, o.coarse_scores):
+        if _margin(f, s, masks, floor) < 2 * QMI_TOL:
+            return True
+    for rank, k in enumerate(o.peaks or []):
+        lo, hi = O.fine_window(grid, k)
+        for f, s in zip(O.linear_grid(lo, hi, KW["n_fine"]), o.fine_scores[rank]):
+            if _margin(f, s, masks, floor) < 2 * QMI_TOL:
+                return True
+    return False
+
+
+def _masks_for(p0, top, best):
+    """A mask over the unmasked best period p0, above every score (top is the highest), plus the
+    table's masks up to 40 days made 20 resolution elements wide, at twice the best score."""
+    table = [m for m in qmi.spurious_masks(2.0 * best, width=20.0) if m[0] <= 40.0]
+    return [(p0, 0.02 * p0, 10.0 * top)] + table
+
+
+def test_masked_search_matches_oracle(ctx):
+    grid = O.linear_grid(KW["f_min"], KW["f_max"], KW["n_coarse"])
+    compared, exact, ties, skipped = 0, 0, [], []
+    for k, c in enumerate(_curves()):
+        o0 = O.best_period(c.t, c.y, c.e, 0.3, O.SIGMA_SILVERMAN, **KW)
+        masks = _masks_for(1.0 / o0.f_best, float(np.nanmax(o0.coarse_scores)), o0.score)
+        o = O.best_period(c.t, c.y, c.e, 0.3, O.SIGMA_SILVERMAN, masks=masks, **KW)
+        ctx.set_masks(masks)
+        r, _ = ctx.best_period([0, c.n], c.t, c.y, c.e, 0.3, **KW)
+        r = r[0]
+        print("curve %d N=%d P0=%.5g -> %.5g (GPU %.5g)" % (k, c.n, 1 / o0.f_best, 1 / o.f_best,
+                                                            1 / r["f_best"]), flush=True)
+        assert r["status"] == 0
+        assert o.f_best != o0.f_best and not O.in_mask(o.f_best, o.score, masks)
+        if _near_edge(o, masks, grid):
+            skipped.append(k)
+            continue
+        compared += 1
+        assert r["n_peaks"] == o.n_peaks and r["coarse_argmax"] == o.coarse_argmax, k
+        if (r["coarse_index"], r["peak_rank"], r["fine_index"]) == (o.coarse_index, o.peak_rank,
+                                                                    o.fine_index):
+            assert r["f_best"] == o.f_best
+            assert abs(r["score"] - o.score) <= QMI_TOL * abs(o.score)
+            exact += 1
+            continue
+        q = O.qmi(O.information_potentials(c.t, c.y, 0.3, o.sigma_y, [r["f_best"]]))[0]
+        assert q >= o.score * (1 - 1e-5) and not O.in_mask(r["f_best"], q, masks), k
+        ties.append(k)
+    ctx.set_masks(None)
+    print("masked search: %d compared (%d identical, ties %s), near a mask edge %s"
+          % (compared, exact, ties, skipped))
+    assert compared >= len(NS) - 3 and exact >= compared - 2
+
+
+def test_masked_bands_match_oracle(ctx):
+    curves = _curves()[:8]
+    b = synth.pack(curves)
+    bk = dict(n_trials=60, n_grid=6000)
+    ctx.set_masks(None)
+    res0, trials0, scores0 = ctx.bands_best_period(b.offsets, b.t, b.y, b.e, 0.3, **bk)
+    compared, skipped, n_masked = 0, [], 0
+    for k, c in enumerate(curves):
+        o0 = O.bands_best_period(c.t, c.y, c.e, 0.3, O.SIGMA_SILVERMAN, **bk)
+        masks = _masks_for(1.0 / o0["f_best"], float(np.nanmax(o0["scores"])), o0["score"])
+        o = O.bands_best_period(c.t, c.y, c.e, 0.3, O.SIGMA_SILVERMAN, masks=masks, **bk)
+        ctx.set_masks(masks)
+        res, trials, scores = ctx.bands_best_period([0, c.n], c.t, c.y, c.e, 0.3, **bk)
+        # masks change only the selection
+        assert np.array_equal(trials[0], trials0[k], equal_nan=True)
+        assert np.array_equal(scores[0], scores0[k], equal_nan=True)
+        assert res[0]["status"] == 0 and res[0]["n_peaks"] == res0[k]["n_peaks"]
+        f, q = o["freqs"], o["scores"]
+        floor = 1e-3 * float(np.nanmax(np.abs(q)))
+        n_masked += sum(O.in_mask(x, v, masks) for x, v in zip(f, q))
+        assert o["f_best"] != o0["f_best"]
+        if min(_margin(x, v, masks, floor) for x, v in zip(f, q)) < 2 * QMI_TOL:
+            skipped.append(k)
+            continue
+        compared += 1
+        got = trials[0][res[0]["coarse_index"]]
+        assert got == res[0]["f_best"]
+        if got == o["f_best"]:
+            assert abs(res[0]["score"] - o["score"]) <= QMI_TOL * abs(o["score"])
+            continue
+        # the trial lists may differ by a window near-tie (test_gpu_bands); the GPU's choice must
+        # then be unmasked and as good as the oracle's best
+        qg = O.qmi(O.information_potentials(c.t, c.y, 0.3, o["sigma_y"], [got]))[0]
+        assert qg >= o["score"] * (1 - 1e-5) and not O.in_mask(got, qg, masks), k
+    ctx.set_masks(None)
+    print("bands: %d compared, near a mask edge %s, %d oracle trials inside a mask"
+          % (compared, skipped, n_masked))
+    assert compared >= len(curves) - 2 and n_masked > len(curves)
+
+
+def test_everything_masked_and_graph_replay(ctx):
+    c = synth.survey_batch_curve(3, n=200)
+    kw = dict(KW, n_coarse=500)
+    with qmi.Context(0) as g:
+        r0, _ = g.best_period([0, c.n], c.t, c.y, c.e, 0.3, **kw)
+        r0b, _ = g.best_period([0, c.n], c.t, c.y, c.e, 0.3, **kw)  # replayed graph
+        assert g.stats()["used_graph"] == 1 and r0.tobytes() == r0b.tobytes()
+        g.set_masks([(1.0, 1e6, 1e30)])  # covers every candidate
+        r1, _ = g.best_period([0, c.n], c.t, c.y, c.e, 0.3, **kw)
+        assert r1["status"][0] == 0 and math.isnan(r1["f_best"][0])
+        assert r1["coarse_argmax"][0] == -1 and r1["n_peaks"][0] == 0
+        b1, _, _ = g.bands_best_period([0, c.n], c.t, c.y, c.e, 0.3, n_trials=20, n_grid=2000)
+        assert math.isnan(b1["f_best"][0]) and b1["n_peaks"][0] > 0
+        g.set_masks(None)
+        r2, _ = g.best_period([0, c.n], c.t, c.y, c.e, 0.3, **kw)
+        assert r2.tobytes() == r0.tobytes()
+
+
+def test_set_masks_arguments(ctx):
+    for bad in ([(0.0, 1.0, 1.0)], [(1.0, 0.0, 1.0)], [(1.0, 1.0, math.inf)],
+                [(math.nan, 1.0, 1.0)], [(1.0, 1.0, 1.0)] * (qmi.MAX_MASKS + 1)):
+        with pytest.raises(qmi.QMIError) as ei:
+            ctx.set_masks(bad)
+        assert ei.value.code == qmi.EINVAL
+    ctx.set_masks([(1.0, 1.0, 1.0)] * qmi.MAX_MASKS)
+    ctx.set_masks(None)
+
+
+def test_serving_applies_the_masks():
+    curves = [synth.serving_curve(k) for k in range(6)]
+    kw = dict(KW, n_coarse=800)
+    masks = [m for m in qmi.spurious_masks(0.3, width=20.0) if m[0] <= 40.0]
+    with qmi.Context(0) as c:
+        c.set_masks(masks)
+        b = synth.pack(curves)
+        want, _ = c.best_period(b.offsets, b.t, b.y, b.e, 0.3, **kw)
+        c.serve_start(0.3, max_batch=4, max_inflight=2, **kw)
+        with pytest.raises(qmi.QMIError):
+            c.set_masks(None)  # not while serving
+        got = {}
+        for k, cv in enumerate(curves):
+            while not c.submit(cv.t, cv.y, cv.e, tag=k):
+                res, tags = c.poll(16, 1000)
+                got.update({int(t): r for t, r in zip(tags, res)})
+        import time
+        t0 = time.time()
+        while len(got) < len(curves) and time.time() - t0 < 60:
+            res, tags = c.poll(16, 10000)
+            got.update({int(t): r for t, r in zip(tags, res)})
+        c.serve_stop()
+    assert len(got) == len(curves)
+    for k in range(len(curves)):
+        assert np.array_equal(got[k], want[k]), k
