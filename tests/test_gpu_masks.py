@@ -96,6 +96,35 @@ def test_masked_search_matches_oracle(ctx):
     assert compared >= len(NS) - 3 and exact >= compared - 2
 
 
+@pytest.mark.parametrize("mode", ["fp64", "nckp", "no_refinement"])
+def test_masked_search_other_modes(ctx, mode):
+    """The filter in the FP64 path, with nCKP as the searched score, and without refinement (the
+    coarse argmax outside the masks)."""
+    kw = dict(KW, n_coarse=1500)
+    score = O.SCORE_NCKP if mode == "nckp" else O.SCORE_QMI
+    if mode == "no_refinement":
+        kw.update(top_k=0, n_fine=0)
+    prec = qmi.PREC_FP64 if mode == "fp64" else qmi.PREC_MIXED
+    grid = O.linear_grid(kw["f_min"], kw["f_max"], kw["n_coarse"])
+    exact = 0
+    curves = _curves()[:4]
+    for k, c in enumerate(curves):
+        o0 = O.best_period(c.t, c.y, c.e, 0.3, O.SIGMA_SILVERMAN, score=score, **kw)
+        masks = _masks_for(1.0 / o0.f_best, float(np.nanmax(o0.coarse_scores)), o0.score)
+        o = O.best_period(c.t, c.y, c.e, 0.3, O.SIGMA_SILVERMAN, score=score, masks=masks, **kw)
+        assert o.f_best != o0.f_best
+        ctx.set_masks(masks)
+        r, _ = ctx.best_period([0, c.n], c.t, c.y, c.e, 0.3, score=score, precision=prec, **kw)
+        r = r[0]
+        if _near_edge(o, masks, grid):
+            continue
+        assert r["n_peaks"] == o.n_peaks and r["coarse_argmax"] == o.coarse_argmax, (mode, k)
+        if r["f_best"] == o.f_best:
+            exact += 1
+    ctx.set_masks(None)
+    assert exact >= len(curves) - 1, (mode, exact)
+
+
 def test_masked_bands_match_oracle(ctx):
     curves = _curves()[:8]
     b = synth.pack(curves)
