@@ -394,8 +394,9 @@ __device__ __forceinline__ void pair_term(R hc, R hs, R ux, R uy, R moff, R k, R
 // over the same rows in the same order, so that SJ is 0 and the scores come out exactly.
 // Variants (chosen by the host autotuner): WPE is the occupancy target in waves per SIMD (2: the
 // registers of 2 waves, no spills; 4: at most 128 VGPRs, so two workgroups share a CU), CH the
-// columns per LDS chunk.
-template <typename R, int WPE, int CH, bool FOLD32 = false>
+// columns per LDS chunk.  PULLK (per-curve frequency lists) reads each column's K block while
+// staging it.
+template <typename R, int WPE, int CH, bool FOLD32 = false, bool PULLK = false>
 __global__ void __launch_bounds__(kThreads, WPE)
 pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ order,
              FreqPlan fp, const double* __restrict__ t_all, const R* __restrict__ K_all,
@@ -486,9 +487,20 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
         const R* ksb = ks_all + P.ksoff + (int64_t)((base / PASS) * kWaves + w) * n;
         const int nch = (n - base + CH - 1) / CH;
 
+        // With per-curve frequency lists (a few tiles per curve, as in the bands method) the
+        // workgroups of a curve run side by side and every column's scalar K loads would miss the
+        // L2; staging a column then also reads its 1 KB K block of this pass (16 bytes per lane,
+        // padding rows included), a chunk before the column is used.  The value only feeds an
+        // empty asm statement, which keeps the load and changes nothing.
+        constexpr bool pull_k = PULLK && sizeof(R) == 4;
         auto stage = [&](int j0, int buf) {
             for (int q = w; q < CH; q += kWaves) {
                 const int j = j0 + q;
+                if (pull_k && j < n) {
+                    const float4 kb = reinterpret_cast<const float4*>(
+                        K_all + P.koff + (int64_t)j * P.npad + base)[lane];
+                    asm volatile("" ::"v"(kb.x));
+                }
                 ph[buf][q][lane] = (j < n) ? W::at(fq[w][lane], t[j], scale) : V{R(0), R(0)};
             }
         };
@@ -665,12 +677,12 @@ struct PairGrid {
     int xcd_grouped;
 };
 
-template <typename R, int WPE, int CH, bool FOLD32 = false>
+template <typename R, int WPE, int CH, bool FOLD32 = false, bool PULLK = false>
 static hipError_t launch_pairs_v(hipStream_t st, const CurveParams* cp, const int32_t* order,
                                  const PairGrid& g, const FreqPlan& fp, const double* t,
                                  const R* K, const double* r, const double* rp, const R* ks,
                                  const PairOut& out) {
-    pairs_kernel<R, WPE, CH, FOLD32><<<g.blocks, kThreads, 0, st>>>(
+    pairs_kernel<R, WPE, CH, FOLD32, PULLK><<<g.blocks, kThreads, 0, st>>>(
         cp, order, fp, t, K, r, rp, ks, g.n_work, g.xcd_grouped, out);
     return hipGetLastError();
 }
@@ -691,6 +703,23 @@ hipError_t launch_pairs(hipStream_t st, const CurveParams* cp, const int32_t* or
                                        : (int64_t)n_work_curves;
     g.blocks = (unsigned)(rows * tiles);
     if constexpr (sizeof(R) == 4) {
+        // Per-curve lists have few tiles per curve: their launches use the K-pulling instances.
+        if (fp.kind == 3 && variant != kVariantFold32) {
+            switch (variant) {
+                case 1:
+                    return launch_pairs_v<R, 4, 64, false, true>(st, cp, order, g, fp, t, K, r,
+                                                                 rp, ks, out);
+                case 2:
+                    return launch_pairs_v<R, 2, 32, false, true>(st, cp, order, g, fp, t, K, r,
+                                                                 rp, ks, out);
+                case 3:
+                    return launch_pairs_v<R, 4, 32, false, true>(st, cp, order, g, fp, t, K, r,
+                                                                 rp, ks, out);
+                default:
+                    return launch_pairs_v<R, 2, 64, false, true>(st, cp, order, g, fp, t, K, r,
+                                                                 rp, ks, out);
+            }
+        }
         switch (variant) {
             case kVariantFold32:
                 return launch_pairs_v<R, 2, 64, true>(st, cp, order, g, fp, t, K, r, rp, ks, out);
