@@ -17,9 +17,12 @@ written after the last checkpoint) are cut off and that batch is searched again.
 Batches are generated on a producer thread while the device works on the previous one (the
 library call releases the GIL).  Batch size is a number of curves, chosen large enough that a
 batch fills every compute unit through the tail of the coarse and the refinement launches; the
-pair-kernel variant is chosen by the library's autotuner for the batch's length bucket.
+pair-kernel variant is chosen by the library's autotuner for the batch's length bucket.  With
+spurious-period masks (Sec. 6.1) every search of the run leaves out candidates under a mask; the
+masks are part of the run's configuration.
 
     python -m paper_1412_1840_amd.survey --out DIR --curves 125000 [--batch 1024] [--first 0]
+        [--spurious-amplitude A [--spurious-width W]]
 """
 from __future__ import annotations
 
@@ -59,7 +62,8 @@ class SurveyRunner:
 
     def __init__(self, out_dir: str, n_curves: int, source: Callable[[int], synth.Curve],
                  source_name: str, search: dict, sigma_t: float, batch_curves: int = 1024,
-                 first: int = 0, device: int = 0, compute=None, result_dtype=None):
+                 first: int = 0, device: int = 0, compute=None, result_dtype=None,
+                 masks=None):
         if n_curves < 0 or batch_curves < 1:
             raise ValueError("n_curves must be >= 0 and batch_curves >= 1")
         self.out_dir = out_dir
@@ -70,6 +74,9 @@ class SurveyRunner:
         self.config = {"source": source_name, "first": self.first, "n_curves": self.n_curves,
                        "sigma_t": float(sigma_t), "search": dict(search),
                        "batch_curves": self.batch_curves}
+        self.masks = [tuple(float(v) for v in m) for m in (masks or [])]
+        if self.masks:
+            self.config["masks"] = [list(m) for m in self.masks]
         self.search = dict(search)
         self.sigma_t = float(sigma_t)
         self.device = device
@@ -105,6 +112,7 @@ class SurveyRunner:
             # Batches differ in composition, so a captured graph would never be replayed; eager
             # launches also let the library time the pair kernels.
             self._ctx.set_option(qmi.OPT_USE_GRAPH, 0)
+            self._ctx.set_masks(self.masks)
         s = self.search
         res, _ = self._ctx.best_period(batch.offsets, batch.t, batch.y, batch.e, self.sigma_t,
                                        f_min=s["f_min"], f_max=s["f_max"],
@@ -223,11 +231,20 @@ def main(argv=None) -> int:
     ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--max-batches", type=int, default=None)
     ap.add_argument("--device", type=int, default=0)
+    ap.add_argument("--spurious-amplitude", type=float, default=None,
+                    help="mask the table of spurious periods (Sec. 6.1) at this amplitude, in "
+                         "units of the searched score")
+    ap.add_argument("--spurious-width", type=float, default=0.5,
+                    help="mask sigma in Fourier resolution elements of a 2335-day span")
     a = ap.parse_args(argv)
     wl = synth.WORKLOADS[a.source]
     search = {k: wl[k] for k in ("f_min", "f_max", "n_coarse", "top_k", "n_fine")}
+    masks = None
+    if a.spurious_amplitude is not None:
+        from . import qmi
+        masks = qmi.spurious_masks(a.spurious_amplitude, width=a.spurious_width)
     run = SurveyRunner(a.out, a.curves, SOURCES[a.source], a.source, search, wl["sigma_t"],
-                       batch_curves=a.batch, first=a.first, device=a.device)
+                       batch_curves=a.batch, first=a.first, device=a.device, masks=masks)
 
     def log(msg):
         print(msg, flush=True)

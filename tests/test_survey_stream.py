@@ -84,6 +84,18 @@ def test_changed_configuration_is_refused(tmp_path):
         runner(tmp_path, n=30).run()
 
 
+def test_masks_are_part_of_the_configuration(tmp_path):
+    m = [(1.0, 1e-3, 0.5), (29.5305, 0.2, 0.5)]
+    runner(tmp_path, masks=m).run(max_batches=1)
+    ck = json.load(open(os.path.join(str(tmp_path), CHECKPOINT)))
+    assert ck["config"]["masks"] == [list(x) for x in m]
+    assert runner(tmp_path, masks=m).run()["done"] == 23
+    with pytest.raises(ValueError):
+        runner(tmp_path).run()  # the same run without masks is a different configuration
+    with pytest.raises(ValueError):
+        runner(tmp_path, masks=m[:1]).run()
+
+
 def test_empty_and_single_curve_runs(tmp_path):
     assert runner(tmp_path / "e", n=0).run()["done"] == 0
     assert len(runner(tmp_path / "e", n=0).results()) == 0
@@ -130,3 +142,26 @@ def test_survey_command_line(tmp_path, capsys):
     summary = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
     assert summary["curves_done"] == 40 and summary["batches"] == 3 and summary["bad_status"] == 0
     assert summary["roofline_frac_kernel"] is not None
+
+
+@pytest.mark.gpu
+def test_survey_with_spurious_masks_matches_one_masked_call(tmp_path):
+    """--spurious-amplitude: the run's records equal one qmi_best_period call over the same curves
+    with the table's masks set."""
+    from paper_1412_1840_amd import qmi, survey
+
+    out = str(tmp_path / "m")
+    assert survey.main(["--out", out, "--curves", "24", "--batch", "16", "--source",
+                        "survey_batch", "--spurious-amplitude", "0.3",
+                        "--spurious-width", "20"]) == 0
+    got = np.fromfile(os.path.join(out, RESULTS), dtype=qmi.RESULT_DTYPE)
+    wl = synth.WORKLOADS["survey_batch"]
+    kw = {k: wl[k] for k in ("f_min", "f_max", "n_coarse", "top_k", "n_fine")}
+    b = synth.pack([synth.survey_batch_curve(k) for k in range(24)])
+    with qmi.Context(0) as ctx:
+        ctx.set_masks(qmi.spurious_masks(0.3, width=20.0))
+        want, _ = ctx.best_period(b.offsets, b.t, b.y, b.e, wl["sigma_t"], **kw)
+        ctx.set_masks(None)
+        plain, _ = ctx.best_period(b.offsets, b.t, b.y, b.e, wl["sigma_t"], **kw)
+    assert got.tobytes() == want.tobytes()
+    assert not np.array_equal(want["f_best"], plain["f_best"])  # the masks changed some result
