@@ -297,7 +297,7 @@ def in_mask(f: float, s: float, masks) -> bool:
     """True when the candidate (1/f, s) lies under any mask (Sec. 6.1)."""
     if not masks:
         return False
-    P = 1.0 / f
+    P = math.inf if f == 0 else 1.0 / f
     for pk, sk, ak in masks:
         d = P - pk
         if s < ak * math.exp(-(d * d) / (2.0 * sk * sk)):
