@@ -218,6 +218,8 @@ const char *qmi_last_error(const qmi_ctx *ctx);
 /* Options (qmi_set_option). */
 #define QMI_OPT_USE_GRAPH 1 /* 1: capture the device section into a hipGraph and replay it (default 1) */
 #define QMI_OPT_TILE 2      /* pair-kernel variant: 0 autotuned per length bucket, k > 0 variant k-1 */
+/* The autotuner chooses between variants 0 and 1, which give the same bits; variants 2 and 3
+ * (forced with QMI_OPT_TILE 3 or 4) fold their row sums on 32-column chunks and round differently. */
 #define QMI_OPT_SYNC 3      /* reserved */
 int qmi_set_option(qmi_ctx *ctx, int32_t option, int64_t value);
 

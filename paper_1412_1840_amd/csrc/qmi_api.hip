@@ -56,7 +56,7 @@ struct qmi_ctx {
         kT, kY, kE, kCP, kOrder, kRowStart, kK, kR, kRP, kRD, kKS, kCoarse, kCoarse2, kFine, kFine2,
         kIps, kPeakK, kNpk, kWin, kArgmax, kRes, kFreqs, kProbe, kTS, kYS, kBandT, kBandCnt,
         kBandId, kS, kTrials, kTrialK, kPOff, kPStIn, kPCnt, kPSt, kPDet, kPTo, kPYo, kPEo,
-        kPPer, kNumBufs
+        kPPer, kPart, kNumBufs
     };
     Buf bufs[kNumBufs];
     static_assert(kNumBufs <= 64, "one bit per buffer in in_use");
@@ -337,9 +337,9 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
     std::vector<CurveParams> cp(nc);
     std::vector<int32_t> order(nc);
     std::vector<int64_t> row_start(nc);
-    int64_t koff = 0, poff = 0, ksoff = 0, rows = 0;
+    int64_t koff = 0, poff = 0, ksoff = 0, rows = 0, pieces = 0;
     constexpr int kPassR = kWaves * rows_per_wave<R>();
-    int max_n = 2;
+    int max_n = 2, max_pieces = 0;
     for (int32_t i = 0; i < nc; ++i) {
         const int32_t k = g.c0 + i;
         const int64_t a = b->offsets[k], n = b->offsets[k + 1] - a;
@@ -360,6 +360,10 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
             koff += (int64_t)p.n * p.npad;
             poff += p.npad;
             ksoff += (int64_t)((p.n + kPassR - 1) / kPassR) * kWaves * p.n;
+            const int nbp = (p.n + kPassR - 1) / kPassR;
+            p.pqoff = pieces;
+            pieces += (int64_t)nbp * (nbp + 1) / 2;
+            max_pieces = std::max(max_pieces, nbp * (nbp + 1) / 2);
             row_start[i] = rows;
             rows += p.n;
             max_n = std::max(max_n, p.n);
@@ -427,6 +431,22 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
     }
     if (cs.periodogram && !cs.dev_inputs) ENSURE(qmi_ctx::kFreqs, F1 * 8);
 #undef ENSURE
+    // A launch with fewer (curve, 64-frequency tile) items than this cannot fill the chip's 512
+    // workgroup slots several times over; it runs one (pass, column segment) piece per workgroup
+    // instead, with the pieces' sums in a scratch buffer (same bits either way).
+    constexpr int64_t kSplitBelow = 2048;
+    constexpr int64_t kSplitMaxBytes = int64_t(256) << 20;
+    const int64_t tiles1 = (F1 + 63) / 64, tiles2 = (F2 + 63) / 64;
+    const int64_t part_bytes = pieces * std::max(F1, F2) * 24;
+    bool split1 = max_pieces > 1 && nc * tiles1 < kSplitBelow;
+    bool split2 = refine && max_pieces > 1 && nc * tiles2 < kSplitBelow;
+    if ((split1 || split2) &&
+        (part_bytes > kSplitMaxBytes || (size_t)part_bytes > ctx->budget / 8 ||
+         ensure(ctx, qmi_ctx::kPart, part_bytes) != QMI_OK)) {
+        split1 = split2 = false;
+        ctx->err.clear();
+    }
+    double* dpart = (split1 || split2) ? dptr<double>(ctx, qmi_ctx::kPart) : nullptr;
 
     hipStream_t st = ctx->stream;
     const double* t = cs.dev_inputs ? b->t + g.s0 : dptr<double>(ctx, qmi_ctx::kT);
@@ -579,7 +599,12 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
         if (bp) HIP_OK(ctx, launch_bands(st, dcp, nc, max_n, t, y, bd));
         if (events) pair_event_idx.push_back(ctx->ev_used);
         rec();
-        HIP_OK(ctx, launch_pairs<R>(st, dcp, dorder, nc, fp, t, K, rd, rp, ks, po, variant));
+        {
+            PairOut pc1 = po;
+            pc1.part = split1 ? dpart : nullptr;
+            HIP_OK(ctx, launch_pairs<R>(st, dcp, dorder, nc, fp, t, K, rd, rp, ks, pc1, variant,
+                                        split1 ? max_pieces : 0));
+        }
         rec();
         if (bp) {
             HIP_OK(ctx, launch_bands_best(st, dcp, nc, coarse, coarse2, score_kind, bd,
@@ -589,11 +614,12 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
             HIP_OK(ctx, launch_peaks(st, dcp, nc, coarse, s->n_coarse, fp.f0, fp.df, top_k,
                                      std::max(n_fine, 2), ctx->masks, pk));
             if (refine) {
-                PairOut fo{fine, fine2, nullptr, score_kind, 0};
+                PairOut fo{fine, fine2, nullptr, score_kind, 0, split2 ? dpart : nullptr};
                 if (events) pair_event_idx.push_back(ctx->ev_used);
                 rec();
                 HIP_OK(ctx,
-                       launch_pairs<R>(st, dcp, dorder, nc, ff, t, K, rd, rp, ks, fo, variant));
+                       launch_pairs<R>(st, dcp, dorder, nc, ff, t, K, rd, rp, ks, fo, variant,
+                                       split2 ? max_pieces : 0));
                 rec();
             }
             HIP_OK(ctx, launch_best(st, dcp, nc, coarse, coarse2, s->n_coarse, fine, fine2,
@@ -763,8 +789,10 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
         }
     }
     if (tune_now) {
-        // Time every variant on the largest curves of this group (the first in LPT order) over a
-        // slice of the same frequency plan, into a scratch output, and keep the fastest.
+        // Time the 64-column variants (0 and 1, which differ only in occupancy and give the same
+        // bits, so that tuning never changes a result) on the largest curves of this group (the
+        // first in LPT order) over a slice of the same frequency plan, into a scratch output, and
+        // keep the fastest.  The 32-column variants are reached only through QMI_OPT_TILE.
         const int pc = std::min(nc, 48);
         FreqPlan probe = fp;
         probe.count = (int32_t)std::min<int64_t>(F1, 64 * 24);
@@ -778,11 +806,13 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
         HIP_OK(ctx, hipEventCreate(&e1));
         float best_ms = 0.f;
         int best_v = 0;
-        for (int v = 0; v < nvar; ++v) {
-            HIP_OK(ctx, launch_pairs<R>(st, dcp, dorder, pc, probe, t, K, rd, rp, ks, pout, v));
+        for (int v = 0; v < std::min(nvar, 2); ++v) {
+            HIP_OK(ctx,
+                   launch_pairs<R>(st, dcp, dorder, pc, probe, t, K, rd, rp, ks, pout, v, 0));
             HIP_OK(ctx, hipEventRecord(e0, st));
             for (int rep = 0; rep < 2; ++rep)
-                HIP_OK(ctx, launch_pairs<R>(st, dcp, dorder, pc, probe, t, K, rd, rp, ks, pout, v));
+                HIP_OK(ctx,
+                       launch_pairs<R>(st, dcp, dorder, pc, probe, t, K, rd, rp, ks, pout, v, 0));
             HIP_OK(ctx, hipEventRecord(e1, st));
             HIP_OK(ctx, hipEventSynchronize(e1));
             float ms = 0.f;

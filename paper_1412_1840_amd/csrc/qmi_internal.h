@@ -53,6 +53,7 @@ struct CurveParams {
     double psnr;
     double bk;     // diagonal value of the stored K table (B rounded to the kernel type)
     double sjc;    // sum_{i<j} K(i,j)            (FP64, from the stored K table)
+    int64_t pqoff; // first piece of this curve in a one-piece-per-workgroup launch's partial sums
 };
 
 // Rows per wave of the pair kernel for each arithmetic type (a pass is kWaves times this).
@@ -81,6 +82,7 @@ struct PairOut {
     double* ips;     // nullable: [curve][count][3] V_J, IP_t, V_C
     int32_t score_kind;
     int32_t pad;
+    double* part;    // one piece per workgroup: [piece (pqoff + q)][count][3] FP64 piece sums
 };
 
 struct PeakOut {
@@ -170,6 +172,9 @@ template <typename R>
 hipError_t launch_ksum(hipStream_t st, const CurveParams* cp, int n_curves, const R* K, R* ks);
 // Pair-kernel variants: ids 0 .. pair_variants<R>() - 1 (0 is the default), and for R = float
 // kVariantFold32, the shape of variant 0 with the phase fold in FP32 (a precision control).
+// split_pmax > 0 (with out.part): one (pass, column segment) piece per workgroup, at most
+// split_pmax pieces per curve, then the epilogue kernel; 0: every piece of a (curve, tile) in one
+// workgroup.  Both give the same bits.
 constexpr int kVariantFold32 = -1;
 template <typename R>
 int pair_variants();
@@ -177,7 +182,7 @@ template <typename R>
 hipError_t launch_pairs(hipStream_t st, const CurveParams* cp, const int32_t* order,
                         int n_work_curves, const FreqPlan& fp, const double* t, const R* K,
                         const double* rd, const double* rp, const R* ks, const PairOut& out,
-                        int variant);
+                        int variant, int split_pmax);
 hipError_t launch_peaks(hipStream_t st, const CurveParams* cp, int n_curves, const double* coarse,
                         int n_coarse, double f0, double df, int top_k, int n_fine,
                         const MaskDev& md, const PeakOut& po);

@@ -383,6 +383,26 @@ __device__ __forceinline__ void pair_term(R hc, R hs, R ux, R uy, R moff, R k, R
     J = fma(k, g, J);
 }
 
+// The epilogue of a (curve, slot): V_J, IP_t, V_C from the FP64 pair sums and the Gram-stage
+// constants, then QMI and nCKP (Sec. 3).
+__device__ __forceinline__ void pair_scores(const CurveParams& P, double SJ, double ST, double SC,
+                                            int64_t obase, const PairOut& out) {
+    const double N = (double)P.n;
+    const double VJ = P.A * (N * P.bk + 2.0 * (P.sjc + SJ)) / (N * N);
+    const double IPt = P.A * (N + 2.0 * ST) / (N * N);
+    const double VC = P.A * (P.rsum + SC) / (N * N * N);
+    const double VM = P.ipy * IPt;
+    const double q = log(VJ) + log(VM) - 2.0 * log(VC);
+    const double nckp = sqrt(N * P.sigma_t) / P.ipy * (VJ - VM);
+    out.score[obase] = out.score_kind == 0 ? q : nckp;
+    if (out.score2) out.score2[obase] = out.score_kind == 0 ? nckp : q;
+    if (out.ips) {
+        out.ips[obase * 3 + 0] = VJ;
+        out.ips[obase * 3 + 1] = IPt;
+        out.ips[obase * 3 + 2] = VC;
+    }
+}
+
 // One work item = (curve, kLanes frequency slots).  Accumulators per lane (one frequency), FP64:
 //   ST  = sum_{i<j} g_ij                 SJ  = sum_{i<j} K(i,j) g_ij - sum_{i<j} K(i,j)
 //   SC  = sum_{i<j} (r_i + r_j) g_ij
@@ -392,24 +412,33 @@ __device__ __forceinline__ void pair_term(R hc, R hs, R ux, R uy, R moff, R k, R
 // values are 1 (coincident phases, f = 0) every R sum is exact: the column sums of g and the row
 // sums are integers, and the K-weighted column sum equals, bit for bit, the precomputed sum of K
 // over the same rows in the same order, so that SJ is 0 and the scores come out exactly.
+// Summation order.  The work of a (curve, tile) is cut into pieces (pass p, column segment s >= p),
+// a segment being the PASS columns [s PASS, (s + 1) PASS): a piece's sums are its waves' sums added
+// in wave order, and the totals are the pieces' sums added in the order (0,0), (0,1), ..., (1,1),
+// ....  A workgroup either runs every piece of its (curve, tile) and adds each into the totals
+// (part == nullptr), or - in a launch with too few (curve, tile) items to fill the chip - runs a
+// single piece and stores its sums in part, for pair_epilogue_kernel to add in the same order:
+// both give the same bits.
 // Variants (chosen by the host autotuner): WPE is the occupancy target in waves per SIMD (2: the
 // registers of 2 waves, no spills; 4: at most 128 VGPRs, so two workgroups share a CU), CH the
 // columns per LDS chunk.  PULLK (per-curve frequency lists) reads each column's K block while
-// staging it.
-template <typename R, int WPE, int CH, bool FOLD32 = false, bool PULLK = false>
+// staging it.  SPLIT: one piece per workgroup.
+template <typename R, int WPE, int CH, bool FOLD32 = false, bool PULLK = false, bool SPLIT = false>
 __global__ void __launch_bounds__(kThreads, WPE)
 pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ order,
              FreqPlan fp, const double* __restrict__ t_all, const R* __restrict__ K_all,
              const double* __restrict__ rd_all, const double* __restrict__ rp_all,
-             const R* __restrict__ ks_all, int n_work, int xcd_grouped, PairOut out) {
+             const R* __restrict__ ks_all, int n_work, int xcd_grouped, int split_pmax,
+             PairOut out) {
     using W = Warp<R, FOLD32>;
     using V = typename W::V;
     constexpr int ROWS = rows_per_wave<R>();
     constexpr int PASS = kWaves * ROWS;
     constexpr int GRP = 4;  // rows skipped together in the diagonal region
     __shared__ V ph[2][CH][kLanes];
-    __shared__ double fq[kWaves][kLanes];  // the lane's frequency, re-read where the warp is formed
-    __shared__ double acc[3][kWaves][kLanes];  // this lane's SJ, ST, SC (added to in place)
+    __shared__ double fq[kLanes];  // the lane's frequency, re-read where the warp is formed
+    __shared__ double acc[3][kWaves][kLanes];  // this piece's SJ, ST, SC per wave (added to in place)
+    __shared__ double tot[3][kLanes];          // totals over the pieces done so far (wave x: x)
 
     const int lane = threadIdx.x & 63;
     const int w = uniform((int)(threadIdx.x >> 6));
@@ -419,8 +448,15 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
     // (work ranks x, x + kXcds, ...) with their frequency tiles in consecutive blocks, so that a
     // curve's K table is fetched into one L2 only; the grid is then padded to a multiple of kXcds
     // curves.  Otherwise consecutive blocks are the tiles of one curve, spread over all XCDs.
-    int rank, tile;
-    if (xcd_grouped) {
+    int rank, tile, piece = -1;
+    if (SPLIT) {
+        // One piece per workgroup: blocks are (rank, piece, tile), pieces of a curve in order.
+        const int per_rank = split_pmax * tiles;
+        rank = (int)(blockIdx.x / (unsigned)per_rank);
+        const int rem = (int)(blockIdx.x - (unsigned)rank * per_rank);
+        piece = rem / tiles;
+        tile = rem - piece * tiles;
+    } else if (xcd_grouped) {
         const int xcd = (int)(blockIdx.x % kXcds);
         const int seq = (int)(blockIdx.x / kXcds);
         rank = (seq / tiles) * kXcds + xcd;
@@ -435,6 +471,21 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
     const int slot = tile * kLanes + lane;
     bool active;
     const double f = slot_freq(fp, c, slot, active);
+
+    const int nb = (P.n + PASS - 1) / PASS;  // passes (and column segments)
+    int p_lo = 0, p_hi = nb, s_only = -1;
+    if (SPLIT) {
+        // A curve with a bad status has its outputs written by the epilogue kernel.
+        if (P.status != 0 || piece >= nb * (nb + 1) / 2) return;
+        int pp = 0, q = piece;
+        while (q >= nb - pp) {
+            q -= nb - pp;
+            ++pp;
+        }
+        p_lo = pp;
+        p_hi = pp + 1;
+        s_only = pp + q;
+    }
 
     if (P.status != 0) {
         const int64_t obase = (int64_t)c * fp.count + slot;
@@ -465,18 +516,20 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
     *aSJ = 0.0;
     *aST = 0.0;
     *aSC = 0.0;
-    // Kept in LDS rather than in two registers across the column loops (each wave reads back only
-    // what it wrote).
-    fq[w][lane] = f;
+    if (w < 3) tot[w][lane] = 0.0;
+    // Kept in LDS rather than in two registers across the column loops.
+    if (w == 0) fq[lane] = f;
+    __syncthreads();
 
-    for (int base = 0; base < n; base += PASS) {
+    const int base_end = SPLIT ? p_hi * PASS : n;
+    for (int base = SPLIT ? p_lo * PASS : 0; base < base_end; base += PASS) {
         // This wave's rows: base + w + kWaves * m, m < nrows.
         const int nrows = uniform(min(ROWS, max(0, (n - base - w + kWaves - 1) / kWaves)));
         R ci[ROWS], si[ROWS], G[ROWS];
 #pragma unroll
         for (int m = 0; m < ROWS; ++m) {
             const int i = base + w + kWaves * m;
-            V u = (m < nrows) ? W::at(fq[w][lane], t[i], scale) : V{R(0), R(0)};
+            V u = (m < nrows) ? W::at(fq[lane], t[i], scale) : V{R(0), R(0)};
             ci[m] = u.x;
             si[m] = u.y;
             G[m] = R(0);
@@ -485,7 +538,10 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
         const R* Kbase = K_all + P.koff + kofs;
         const double* rpb = rp_all + P.poff + kofs;
         const R* ksb = ks_all + P.ksoff + (int64_t)((base / PASS) * kWaves + w) * n;
-        const int nch = (n - base + CH - 1) / CH;
+        // Columns [cbeg, cend): the whole pass, or the piece's segment.
+        const int cbeg = SPLIT ? s_only * PASS : base;
+        const int cend = SPLIT ? min(n, cbeg + PASS) : n;
+        const int nch = (cend - cbeg + CH - 1) / CH;
 
         // With per-curve frequency lists (a few tiles per curve, as in the bands method) the
         // workgroups of a curve run side by side and every column's scalar K loads would miss the
@@ -501,13 +557,18 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
                         K_all + P.koff + (int64_t)j * P.npad + base)[lane];
                     asm volatile("" ::"v"(kb.x));
                 }
-                ph[buf][q][lane] = (j < n) ? W::at(fq[w][lane], t[j], scale) : V{R(0), R(0)};
+                ph[buf][q][lane] = (j < n) ? W::at(fq[lane], t[j], scale) : V{R(0), R(0)};
             }
         };
-        stage(base, 0);
+        stage(cbeg, 0);
         __syncthreads();
-        for (int k = 0; k < nch; ++k) {
-            const int j0 = base + k * CH;
+        // Chunks in segment order: the inner loop runs the chunks of one column segment, the
+        // segment's piece is folded into the totals after it.
+        constexpr int kSegChunks = PASS / CH;
+        for (int k = 0; k < nch;) {
+          const int kend = min(nch, (k / kSegChunks + 1) * kSegChunks);
+          for (; k < kend; ++k) {
+            const int j0 = cbeg + k * CH;
             if (k + 1 < nch) stage(j0 + CH, (k + 1) & 1);
             const int buf = k & 1;
             const int jend = min(CH, n - j0);
@@ -583,33 +644,69 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
             }
             ladd(aSC, sca);
             __syncthreads();
+          }
+          // The segment's piece is complete: its sums, the waves' sums in wave order, are added
+          // to the totals (wave x owns total x), and the waves start the next piece from zero.
+          if (w < 3) {
+              double sp = 0.0;
+              for (int v = 0; v < kWaves; ++v) sp += acc[w][v][lane];
+              tot[w][lane] += sp;
+          }
+          __syncthreads();
+          *aSJ = 0.0;
+          *aST = 0.0;
+          *aSC = 0.0;
         }
     }
 
-    // Combine the waves' partial sums in wave order (deterministic), then the epilogue.
-    __syncthreads();
     if (w != 0 || !active) return;
-    double SJ = 0.0, ST = 0.0, SC = 0.0;
-    for (int v = 0; v < kWaves; ++v) {
-        SJ += acc[0][v][lane];
-        ST += acc[1][v][lane];
-        SC += acc[2][v][lane];
+    if (SPLIT) {
+        double* pp = out.part + (((int64_t)P.pqoff + piece) * fp.count + slot) * 3;
+        pp[0] = tot[0][lane];
+        pp[1] = tot[1][lane];
+        pp[2] = tot[2][lane];
+        return;
     }
+    pair_scores(P, tot[0][lane], tot[1][lane], tot[2][lane], (int64_t)c * fp.count + slot, out);
+}
+
+// Totals and scores of the launches that ran one piece per workgroup: one thread per (curve,
+// slot) adds the pieces' sums in piece order, as the workgroups of the other launches do.
+constexpr int kEpiBlock = 256;
+
+__global__ void __launch_bounds__(kEpiBlock)
+pair_epilogue_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ order,
+                     FreqPlan fp, int n_work, int pass, PairOut out) {
+    const int64_t idx = (int64_t)blockIdx.x * kEpiBlock + threadIdx.x;
+    const int64_t rank = idx / fp.count;
+    if (rank >= n_work) return;
+    const int slot = (int)(idx - rank * fp.count);
+    const int c = order[rank];
+    const CurveParams P = cp[c];
+    bool active;
+    (void)slot_freq(fp, c, slot, active);
+    if (!active) return;
     const int64_t obase = (int64_t)c * fp.count + slot;
-    const double N = (double)n;
-    const double VJ = P.A * (N * P.bk + 2.0 * (P.sjc + SJ)) / (N * N);
-    const double IPt = P.A * (N + 2.0 * ST) / (N * N);
-    const double VC = P.A * (P.rsum + SC) / (N * N * N);
-    const double VM = P.ipy * IPt;
-    const double q = log(VJ) + log(VM) - 2.0 * log(VC);
-    const double nckp = sqrt(N * P.sigma_t) / P.ipy * (VJ - VM);
-    out.score[obase] = out.score_kind == 0 ? q : nckp;
-    if (out.score2) out.score2[obase] = out.score_kind == 0 ? nckp : q;
-    if (out.ips) {
-        out.ips[obase * 3 + 0] = VJ;
-        out.ips[obase * 3 + 1] = IPt;
-        out.ips[obase * 3 + 2] = VC;
+    if (P.status != 0) {
+        out.score[obase] = NAN;
+        if (out.score2) out.score2[obase] = NAN;
+        if (out.ips) {
+            out.ips[obase * 3 + 0] = NAN;
+            out.ips[obase * 3 + 1] = NAN;
+            out.ips[obase * 3 + 2] = NAN;
+        }
+        return;
     }
+    const int nb = (P.n + pass - 1) / pass;
+    const int pieces = nb * (nb + 1) / 2;
+    double SJ = 0.0, ST = 0.0, SC = 0.0;
+    for (int q = 0; q < pieces; ++q) {
+        const double* pp = out.part + (((int64_t)P.pqoff + q) * fp.count + slot) * 3;
+        SJ += pp[0];
+        ST += pp[1];
+        SC += pp[2];
+    }
+    pair_scores(P, SJ, ST, SC, obase, out);
 }
 
 }  // namespace
@@ -675,6 +772,7 @@ struct PairGrid {
     unsigned blocks;
     int n_work;
     int xcd_grouped;
+    int split_pmax;
 };
 
 template <typename R, int WPE, int CH, bool FOLD32 = false, bool PULLK = false>
@@ -682,26 +780,20 @@ static hipError_t launch_pairs_v(hipStream_t st, const CurveParams* cp, const in
                                  const PairGrid& g, const FreqPlan& fp, const double* t,
                                  const R* K, const double* r, const double* rp, const R* ks,
                                  const PairOut& out) {
-    pairs_kernel<R, WPE, CH, FOLD32, PULLK><<<g.blocks, kThreads, 0, st>>>(
-        cp, order, fp, t, K, r, rp, ks, g.n_work, g.xcd_grouped, out);
+    if (g.split_pmax > 0)
+        pairs_kernel<R, WPE, CH, FOLD32, PULLK, true><<<g.blocks, kThreads, 0, st>>>(
+            cp, order, fp, t, K, r, rp, ks, g.n_work, g.xcd_grouped, g.split_pmax, out);
+    else
+        pairs_kernel<R, WPE, CH, FOLD32, PULLK, false><<<g.blocks, kThreads, 0, st>>>(
+            cp, order, fp, t, K, r, rp, ks, g.n_work, g.xcd_grouped, g.split_pmax, out);
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_pairs(hipStream_t st, const CurveParams* cp, const int32_t* order,
-                        int n_work_curves, const FreqPlan& fp, const double* t, const R* K,
-                        const double* r, const double* rp, const R* ks, const PairOut& out,
-                        int variant) {
-    if (n_work_curves <= 0 || fp.count <= 0) return hipSuccess;
-    const int64_t tiles = (fp.count + kLanes - 1) / kLanes;
-    // Whole curves per XCD once every XCD gets at least 8 of them (enough to balance the XCDs'
-    // loads in the work order); below that, a curve's tiles spread over the whole chip.
-    PairGrid g;
-    g.n_work = n_work_curves;
-    g.xcd_grouped = n_work_curves >= 8 * kXcds;
-    const int64_t rows = g.xcd_grouped ? (int64_t)(n_work_curves + kXcds - 1) / kXcds * kXcds
-                                       : (int64_t)n_work_curves;
-    g.blocks = (unsigned)(rows * tiles);
+static hipError_t launch_pairs_grid(hipStream_t st, const CurveParams* cp, const int32_t* order,
+                                    const PairGrid& g, const FreqPlan& fp, const double* t,
+                                    const R* K, const double* r, const double* rp, const R* ks,
+                                    const PairOut& out, int variant) {
     if constexpr (sizeof(R) == 4) {
         // Per-curve lists have few tiles per curve: their launches use the K-pulling instances.
         if (fp.kind == 3 && variant != kVariantFold32) {
@@ -733,13 +825,45 @@ hipError_t launch_pairs(hipStream_t st, const CurveParams* cp, const int32_t* or
         return launch_pairs_v<R, 2, 32>(st, cp, order, g, fp, t, K, r, rp, ks, out);
     }
 }
+
+template <typename R>
+hipError_t launch_pairs(hipStream_t st, const CurveParams* cp, const int32_t* order,
+                        int n_work_curves, const FreqPlan& fp, const double* t, const R* K,
+                        const double* r, const double* rp, const R* ks, const PairOut& out,
+                        int variant, int split_pmax) {
+    if (n_work_curves <= 0 || fp.count <= 0) return hipSuccess;
+    const int64_t tiles = (fp.count + kLanes - 1) / kLanes;
+    PairGrid g;
+    g.n_work = n_work_curves;
+    if (split_pmax > 0 && out.part) {
+        // One piece per workgroup, then the epilogue kernel.
+        g.xcd_grouped = 0;
+        g.split_pmax = split_pmax;
+        g.blocks = (unsigned)((int64_t)n_work_curves * split_pmax * tiles);
+        hipError_t e = launch_pairs_grid<R>(st, cp, order, g, fp, t, K, r, rp, ks, out, variant);
+        if (e != hipSuccess) return e;
+        const int64_t threads = (int64_t)n_work_curves * fp.count;
+        pair_epilogue_kernel<<<(unsigned)((threads + kEpiBlock - 1) / kEpiBlock), kEpiBlock, 0,
+                               st>>>(cp, order, fp, n_work_curves,
+                                     kWaves * rows_per_wave<R>(), out);
+        return hipGetLastError();
+    }
+    // Whole curves per XCD once every XCD gets at least 8 of them (enough to balance the XCDs'
+    // loads in the work order); below that, a curve's tiles spread over the whole chip.
+    g.split_pmax = 0;
+    g.xcd_grouped = n_work_curves >= 8 * kXcds;
+    const int64_t rows = g.xcd_grouped ? (int64_t)(n_work_curves + kXcds - 1) / kXcds * kXcds
+                                       : (int64_t)n_work_curves;
+    g.blocks = (unsigned)(rows * tiles);
+    return launch_pairs_grid<R>(st, cp, order, g, fp, t, K, r, rp, ks, out, variant);
+}
 template hipError_t launch_pairs<float>(hipStream_t, const CurveParams*, const int32_t*, int,
                                         const FreqPlan&, const double*, const float*,
                                         const double*, const double*, const float*,
-                                        const PairOut&, int);
+                                        const PairOut&, int, int);
 template hipError_t launch_pairs<double>(hipStream_t, const CurveParams*, const int32_t*, int,
                                          const FreqPlan&, const double*, const double*,
                                          const double*, const double*, const double*,
-                                         const PairOut&, int);
+                                         const PairOut&, int, int);
 
 }  // namespace qmi

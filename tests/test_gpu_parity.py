@@ -383,6 +383,34 @@ def test_serving_results_equal_alone(ctx):
         assert np.array_equal(got[k], mixed[k]), k
 
 
+def test_one_piece_per_workgroup_launches_give_the_same_bits(ctx):
+    """A call with too few (curve, 64-frequency tile) items to fill the chip runs one (pass, column
+    segment) piece per workgroup and adds the pieces' sums in an epilogue kernel; a large enough
+    batch runs every piece of a (curve, tile) in one workgroup.  Both add the pieces in the same
+    order, so a curve's coarse periodogram and search result are the same bits either way."""
+    ns = [1000, 257, 600, 513, 300, 900, 777, 2, 256, 1500]
+    curves = [synth.survey_batch_curve(k, n=n) for k, n in enumerate(ns)]
+    kw = dict(f_min=1e-3, f_max=10.0, n_coarse=20000, top_k=10, n_fine=1000)
+    b = pack(curves)
+    big, cbig = ctx.best_period(b.offsets, b.t, b.y, b.e, 0.3, want_coarse=True, **kw)
+    for k, c in enumerate(curves):
+        r, cc = ctx.best_period([0, c.n], c.t, c.y, c.e, 0.3, want_coarse=True, **kw)
+        assert np.array_equal(cc[0], cbig[k], equal_nan=True), k
+        assert r.tobytes() == big[k:k + 1].tobytes(), k
+    # refinement windows and periodograms of both kinds, mixed and FP64
+    freqs = O.linear_grid(1e-3, 10.0, 1500)
+    many = pack([synth.survey_batch_curve(k, n=300 + 7 * k) for k in range(90)])
+    for prec in (qmi.PREC_MIXED, qmi.PREC_FP64):
+        sc, ips, _, _ = ctx.periodogram(many.offsets, many.t, many.y, many.e, freqs, 0.3,
+                                        precision=prec, want_ips=True)
+        for k in (0, 41, 89):
+            lo, hi = many.offsets[k], many.offsets[k + 1]
+            s1, i1, _, _ = ctx.periodogram([0, hi - lo], many.t[lo:hi], many.y[lo:hi],
+                                           many.e[lo:hi], freqs, 0.3, precision=prec,
+                                           want_ips=True)
+            assert np.array_equal(s1[0], sc[k]) and np.array_equal(i1[0], ips[k]), (prec, k)
+
+
 def test_pair_kernel_variants_agree(ctx):
     """Every pair-kernel variant the autotuner can pick meets the oracle bar; variants that differ
     only in occupancy give identical bits."""
