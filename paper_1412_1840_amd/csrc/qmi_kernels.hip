@@ -648,9 +648,12 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
           // The segment's piece is complete: its sums, the waves' sums in wave order, are added
           // to the totals (wave x owns total x), and the waves start the next piece from zero.
           if (w < 3) {
+              // (the lane index formed again, as at the end of the kernel)
+              const int lf =
+                  (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
               double sp = 0.0;
-              for (int v = 0; v < kWaves; ++v) sp += acc[w][v][lane];
-              tot[w][lane] += sp;
+              for (int v = 0; v < kWaves; ++v) sp += acc[w][v][lf];
+              tot[w][lf] += sp;
           }
           __syncthreads();
           *aSJ = 0.0;
@@ -660,14 +663,18 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
     }
 
     if (w != 0 || !active) return;
+    // The lane and slot are formed again here (from the lane count, not threadIdx) so that they
+    // need not stay in registers across the loops.
+    const int ln = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+    const int slot_e = tile * kLanes + ln;
     if (SPLIT) {
-        double* pp = out.part + (((int64_t)P.pqoff + piece) * fp.count + slot) * 3;
-        pp[0] = tot[0][lane];
-        pp[1] = tot[1][lane];
-        pp[2] = tot[2][lane];
+        double* pp = out.part + (((int64_t)P.pqoff + piece) * fp.count + slot_e) * 3;
+        pp[0] = tot[0][ln];
+        pp[1] = tot[1][ln];
+        pp[2] = tot[2][ln];
         return;
     }
-    pair_scores(P, tot[0][lane], tot[1][lane], tot[2][lane], (int64_t)c * fp.count + slot, out);
+    pair_scores(P, tot[0][ln], tot[1][ln], tot[2][ln], (int64_t)c * fp.count + slot_e, out);
 }
 
 // Totals and scores of the launches that ran one piece per workgroup: one thread per (curve,
