@@ -29,88 +29,118 @@ __device__ __forceinline__ double grid_f(double f0, double df, int k) {
     return __dadd_rn(f0, __dmul_rn((double)k, df));
 }
 
+// The wave's best (score, index) by the rank order of better(), in every lane (butterfly).
+__device__ __forceinline__ void wave_best(double& q, int& k) {
+    for (int o = 32; o > 0; o >>= 1) {
+        const double q2 = __shfl_xor(q, o, 64);
+        const int k2 = __shfl_xor(k, o, 64);
+        if (better(q2, k2, q, k)) {
+            q = q2;
+            k = k2;
+        }
+    }
+}
+
+// The block's best of the waves' bests, in every thread; slot (0 or 1) alternates between
+// consecutive calls so that one barrier per call suffices.
+template <int NW>
+__device__ __forceinline__ int block_best(double q, int k, double (*wq)[NW], int (*wk)[NW],
+                                          int slot) {
+    wave_best(q, k);
+    if ((threadIdx.x & 63) == 0) {
+        wq[slot][threadIdx.x >> 6] = q;
+        wk[slot][threadIdx.x >> 6] = k;
+    }
+    __syncthreads();
+    double bq = wq[slot][0];
+    int bk = wk[slot][0];
+    for (int v = 1; v < NW; ++v)
+        if (better(wq[slot][v], wk[slot][v], bq, bk)) {
+            bq = wq[slot][v];
+            bk = wk[slot][v];
+        }
+    return bk;
+}
+
 __global__ void __launch_bounds__(kPeakBlock)
 peaks_kernel(const CurveParams* __restrict__ cp, const double* __restrict__ coarse, int F,
              double f0, double df, int top_k, int n_fine, MaskDev md, PeakOut po) {
-    __shared__ double sq[kPeakBlock];
-    __shared__ int sk[kPeakBlock];
+    constexpr int NW = kPeakBlock / 64;
+    __shared__ double wq[2][NW];
+    __shared__ int wk[2][NW];
     __shared__ int chosen[64];
-    extern __shared__ double peak_dyn[];  // [kPeakBlock][max(top_k, 1)] scores, then indices
+    extern __shared__ double peak_dyn[];  // [max(top_k, 1)][kPeakBlock] scores, then indices
     const int c = blockIdx.x;
     const double* q = coarse + (int64_t)c * F;
     const bool ok = cp[c].status == 0;
-    // Coarse argmax (ties to lower k) over the candidates outside every mask.
+    // One scan of the coarse scores gives both this thread's candidate for the coarse argmax (ties
+    // to lower k, candidates outside every mask) and its best top_k local maxima, kept sorted in
+    // rank order (score descending, ties to the lower k) in its own LDS slots.  The scan takes
+    // kUnroll grid points per step with their loads issued together.
+    constexpr int kUnroll = 4;
+    const int TK = top_k > 0 ? top_k : 1;
+    // Entry i of a thread's list sits at i * kPeakBlock + thread (consecutive threads in
+    // consecutive slots, so that the list operations of a wave do not conflict on LDS banks).
+    double* mv0 = reinterpret_cast<double*>(peak_dyn) + threadIdx.x;
+    int* mk0 = reinterpret_cast<int*>(reinterpret_cast<double*>(peak_dyn) + kPeakBlock * TK) +
+               threadIdx.x;
+    auto mv = [&](int i) -> double& { return mv0[i * kPeakBlock]; };
+    auto mk = [&](int i) -> int& { return mk0[i * kPeakBlock]; };
+    int n_loc = 0;
     double bq = NAN;
     int bk = 0x7fffffff;
-    if (ok)
-        for (int k = threadIdx.x; k < F; k += kPeakBlock)
-            if (better(q[k], k, bq, bk) && !in_mask(md, grid_f(f0, df, k), q[k])) {
-                bq = q[k];
-                bk = k;
+    if (ok) {
+        for (int k0 = threadIdx.x; k0 < F; k0 += kUnroll * kPeakBlock) {
+            double v[kUnroll], lft[kUnroll], rgt[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int k = k0 + u * kPeakBlock;
+                v[u] = k < F ? q[k] : NAN;
+                lft[u] = (k < F && k > 0) ? q[k - 1] : NAN;
+                rgt[u] = (k + 1 < F) ? q[k + 1] : NAN;
             }
-    sq[threadIdx.x] = bq;
-    sk[threadIdx.x] = bk;
-    __syncthreads();
-    for (int s = kPeakBlock / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s && better(sq[threadIdx.x + s], sk[threadIdx.x + s], sq[threadIdx.x],
-                                      sk[threadIdx.x])) {
-            sq[threadIdx.x] = sq[threadIdx.x + s];
-            sk[threadIdx.x] = sk[threadIdx.x + s];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) po.argmax[c] = (sk[0] == 0x7fffffff) ? -1 : sk[0];
-    __syncthreads();
-    // The top_k local maxima: every thread keeps the best top_k of the maxima it scans, sorted
-    // (rank order: score descending, ties to the lower k), in its own LDS slots; then top_k rounds
-    // take the best head among the threads.  The result is the top_k of all maxima in rank order.
-    const int TK = top_k > 0 ? top_k : 1;
-    double* mv = reinterpret_cast<double*>(peak_dyn) + threadIdx.x * TK;
-    int* mk = reinterpret_cast<int*>(reinterpret_cast<double*>(peak_dyn) + kPeakBlock * TK) +
-              threadIdx.x * TK;
-    int n_loc = 0;
-    if (ok && top_k > 0) {
-        for (int k = threadIdx.x; k < F; k += kPeakBlock) {
-            const double v = q[k];
-            bool peak;
-            if (F == 1) peak = (v == v);
-            else if (k == 0) peak = v >= q[1];
-            else if (k == F - 1) peak = v > q[k - 1];
-            else peak = v > q[k - 1] && v >= q[k + 1];
-            if (!peak) continue;
-            if (n_loc == TK && !better(v, k, mv[TK - 1], mk[TK - 1])) continue;
-            if (in_mask(md, grid_f(f0, df, k), v)) continue;
-            int p = n_loc < TK ? n_loc++ : TK - 1;
-            while (p > 0 && better(v, k, mv[p - 1], mk[p - 1])) {
-                mv[p] = mv[p - 1];
-                mk[p] = mk[p - 1];
-                --p;
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int k = k0 + u * kPeakBlock;
+                if (k >= F) break;
+                if (better(v[u], k, bq, bk) && !in_mask(md, grid_f(f0, df, k), v[u])) {
+                    bq = v[u];
+                    bk = k;
+                }
+                if (top_k <= 0) continue;
+                bool peak;
+                if (F == 1) peak = (v[u] == v[u]);
+                else if (k == 0) peak = v[u] >= rgt[u];
+                else if (k == F - 1) peak = v[u] > lft[u];
+                else peak = v[u] > lft[u] && v[u] >= rgt[u];
+                if (!peak) continue;
+                if (n_loc == TK && !better(v[u], k, mv(TK - 1), mk(TK - 1))) continue;
+                if (in_mask(md, grid_f(f0, df, k), v[u])) continue;
+                int p = n_loc < TK ? n_loc++ : TK - 1;
+                while (p > 0 && better(v[u], k, mv(p - 1), mk(p - 1))) {
+                    mv(p) = mv(p - 1);
+                    mk(p) = mk(p - 1);
+                    --p;
+                }
+                mv(p) = v[u];
+                mk(p) = k;
             }
-            mv[p] = v;
-            mk[p] = k;
         }
     }
+    int slot = 0;
+    const int am = block_best<NW>(bq, bk, wq, wk, slot);
+    slot ^= 1;
+    if (threadIdx.x == 0) po.argmax[c] = (am == 0x7fffffff) ? -1 : am;
+    // top_k rounds take the best head among the threads' lists: the top_k of all maxima in rank
+    // order.
     int count = 0, head = 0;
     for (int p = 0; p < top_k && ok; ++p) {
-        bq = head < n_loc ? mv[head] : NAN;
-        bk = head < n_loc ? mk[head] : 0x7fffffff;
-        sq[threadIdx.x] = bq;
-        sk[threadIdx.x] = bk;
-        __syncthreads();
-        for (int s = kPeakBlock / 2; s > 0; s >>= 1) {
-            if (threadIdx.x < s && better(sq[threadIdx.x + s], sk[threadIdx.x + s],
-                                          sq[threadIdx.x], sk[threadIdx.x])) {
-                sq[threadIdx.x] = sq[threadIdx.x + s];
-                sk[threadIdx.x] = sk[threadIdx.x + s];
-            }
-            __syncthreads();
-        }
-        const int kk = sk[0];
-        __syncthreads();
+        const int kk = block_best<NW>(head < n_loc ? mv(head) : NAN,
+                                      head < n_loc ? mk(head) : 0x7fffffff, wq, wk, slot);
+        slot ^= 1;
         if (kk == 0x7fffffff) break;
-        if (head < n_loc && mk[head] == kk) ++head;  // grid indices belong to one thread each
+        if (head < n_loc && mk(head) == kk) ++head;  // grid indices belong to one thread each
         if (threadIdx.x == 0) chosen[count] = kk;
-        __syncthreads();
         ++count;
     }
     if (threadIdx.x == 0) {
