@@ -363,6 +363,15 @@ struct Warp<double, false> {
 };
 
 
+// The lane index, formed afresh from the lane count.  The empty asm keeps the compiler from
+// reusing an earlier copy, so that no register holds the lane index (or an address derived from
+// it) across the pair kernel's loops only to be spilled.
+__device__ __forceinline__ int fresh_lane() {
+    int l = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+    asm volatile("" : "+v"(l));
+    return l;
+}
+
 // Adds v to a lane-private LDS accumulator without returning the old value (ds_add_f64).
 __device__ __forceinline__ void ladd(double* p, double v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
@@ -434,7 +443,7 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
     using V = typename W::V;
     constexpr int ROWS = rows_per_wave<R>();
     constexpr int PASS = kWaves * ROWS;
-    constexpr int GRP = 4;  // rows skipped together in the diagonal region
+    constexpr int GRP = 2;  // rows skipped together in the diagonal region
     __shared__ V ph[2][CH][kLanes];
     __shared__ double fq[kLanes];  // the lane's frequency, re-read where the warp is formed
     __shared__ double acc[3][kWaves][kLanes];  // this piece's SJ, ST, SC per wave (added to in place)
@@ -552,12 +561,13 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
         auto stage = [&](int j0, int buf) {
             for (int q = w; q < CH; q += kWaves) {
                 const int j = j0 + q;
+                const int ls = fresh_lane();
                 if (pull_k && j < n) {
                     const float4 kb = reinterpret_cast<const float4*>(
-                        K_all + P.koff + (int64_t)j * P.npad + base)[lane];
+                        K_all + P.koff + (int64_t)j * P.npad + base)[ls];
                     asm volatile("" ::"v"(kb.x));
                 }
-                ph[buf][q][lane] = (j < n) ? W::at(fq[lane], t[j], scale) : V{R(0), R(0)};
+                ph[buf][q][ls] = (j < n) ? W::at(fq[ls], t[j], scale) : V{R(0), R(0)};
             }
         };
         stage(cbeg, 0);
@@ -648,9 +658,7 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
           // The segment's piece is complete: its sums, the waves' sums in wave order, are added
           // to the totals (wave x owns total x), and the waves start the next piece from zero.
           if (w < 3) {
-              // (the lane index formed again, as at the end of the kernel)
-              const int lf =
-                  (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+              const int lf = fresh_lane();
               double sp = 0.0;
               for (int v = 0; v < kWaves; ++v) sp += acc[w][v][lf];
               tot[w][lf] += sp;
@@ -663,9 +671,9 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
     }
 
     if (w != 0 || !active) return;
-    // The lane and slot are formed again here (from the lane count, not threadIdx) so that they
-    // need not stay in registers across the loops.
-    const int ln = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+    // The lane and slot are formed again here so that they need not stay in registers across
+    // the loops.
+    const int ln = fresh_lane();
     const int slot_e = tile * kLanes + ln;
     if (SPLIT) {
         double* pp = out.part + (((int64_t)P.pqoff + piece) * fp.count + slot_e) * 3;
