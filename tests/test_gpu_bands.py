@@ -147,3 +147,19 @@ def test_bands_maximum_length():
     cv = synth.Curve(t, y, e, True)
     _check_trials(cv, trials[0], rf, 3, 40, 6000)
     assert res[0]["status"] == 0
+
+
+def test_bands_one_piece_launch_gives_the_same_bits():
+    """A batch of 300 curves fills the chip with whole (curve, tile) items (one workgroup runs
+    every piece); a single curve runs one piece per workgroup.  Trials, scores and results agree
+    bit for bit."""
+    curves = [synth.survey_batch_curve(k, n=200 + (k * 37) % 900) for k in range(300)]
+    b = synth.pack(curves)
+    with qmi.Context(0) as c:
+        res, trials, scores = c.bands_best_period(b.offsets, b.t, b.y, b.e, 0.3)
+        for k in (0, 123, 299):
+            cv = curves[k]
+            r1, t1, s1 = c.bands_best_period([0, cv.n], cv.t, cv.y, cv.e, 0.3)
+            assert np.array_equal(t1[0], trials[k], equal_nan=True), k
+            assert np.array_equal(s1[0], scores[k], equal_nan=True), k
+            assert r1[0].tobytes() == res[k].tobytes(), k
