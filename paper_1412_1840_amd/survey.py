@@ -21,7 +21,7 @@ pair-kernel variant is chosen by the library's autotuner for the batch's length 
 spurious-period masks (Sec. 6.1) every search of the run leaves out candidates under a mask; the
 masks are part of the run's configuration.
 
-    python -m paper_1412_1840_amd.survey --out DIR --curves 125000 [--batch 1024] [--first 0]
+    python -m paper_1412_1840_amd.survey --out DIR --curves 125000 [--batch 2048] [--first 0]
         [--spurious-amplitude A [--spurious-width W]]
 """
 from __future__ import annotations
@@ -61,7 +61,7 @@ class SurveyRunner:
     """
 
     def __init__(self, out_dir: str, n_curves: int, source: Callable[[int], synth.Curve],
-                 source_name: str, search: dict, sigma_t: float, batch_curves: int = 1024,
+                 source_name: str, search: dict, sigma_t: float, batch_curves: int = 2048,
                  first: int = 0, device: int = 0, compute=None, result_dtype=None,
                  masks=None):
         if n_curves < 0 or batch_curves < 1:
@@ -228,7 +228,7 @@ def main(argv=None) -> int:
     ap.add_argument("--source", default="survey_stream", choices=sorted(SOURCES))
     ap.add_argument("--curves", type=int, default=125000)
     ap.add_argument("--first", type=int, default=0)
-    ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--batch", type=int, default=2048)
     ap.add_argument("--max-batches", type=int, default=None)
     ap.add_argument("--device", type=int, default=0)
     ap.add_argument("--spurious-amplitude", type=float, default=None,
