@@ -177,11 +177,25 @@ def classification_report(qmi, res, truth):
             "overall": quality(test), "per_snr_bin": per_bin}
 
 
+def kernel_code_digest(root=ROOT):
+    """sha256 of the pair kernel's sources (csrc/qmi_kernels.hip, then csrc/qmi_internal.h) with
+    comments and white space removed, so that editing a comment keeps recorded counters valid."""
+    import hashlib
+    import re
+
+    h = hashlib.sha256()
+    for name in ("qmi_kernels.hip", "qmi_internal.h"):
+        with open(os.path.join(root, "paper_1412_1840_amd", "csrc", name)) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
+    return h.hexdigest()
+
+
 def measured_traffic(workload, n_curves, variant):
     """HBM bytes per pair-kernel launch from the committed counter summary, or None unless the
-    counters were taken on this workload, this variant and the current kernel source."""
-    import hashlib
-
+    counters were taken on this workload, this variant and the current kernel code."""
     path = os.path.join(ROOT, "profiles", "pairs_kernel_survey_batch_4096_traffic.txt")
     if workload != "survey_batch" or n_curves != 4096 or not os.path.exists(path):
         return None
@@ -190,11 +204,7 @@ def measured_traffic(workload, n_curves, variant):
         if "=" in line and not line.lstrip().startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    h = hashlib.sha256()
-    for name in ("qmi_kernels.hip", "qmi_internal.h"):
-        with open(os.path.join(ROOT, "paper_1412_1840_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
-    digest = h.hexdigest()
+    digest = kernel_code_digest()
     if kv.get("kernel_source_sha256") != digest or int(kv.get("variant", -99)) != variant:
         return None
     return float(kv["bytes_per_launch"])

@@ -425,13 +425,13 @@ __device__ __forceinline__ void pair_scores(const CurveParams& P, double SJ, dou
 // a segment being the PASS columns [s PASS, (s + 1) PASS): a piece's sums are its waves' sums added
 // in wave order, and the totals are the pieces' sums added in the order (0,0), (0,1), ..., (1,1),
 // ....  A workgroup either runs every piece of its (curve, tile) and adds each into the totals
-// (part == nullptr), or - in a launch with too few (curve, tile) items to fill the chip - runs a
-// single piece and stores its sums in part, for pair_epilogue_kernel to add in the same order:
-// both give the same bits.
-// Variants (chosen by the host autotuner): WPE is the occupancy target in waves per SIMD (2: the
-// registers of 2 waves, no spills; 4: at most 128 VGPRs, so two workgroups share a CU), CH the
-// columns per LDS chunk.  PULLK (per-curve frequency lists) reads each column's K block while
-// staging it.  SPLIT: one piece per workgroup.
+// (SPLIT false), or - in a launch with too few (curve, tile) items to fill the chip - runs a
+// single piece and stores its sums in out.part, for pair_epilogue_kernel to add in the same order
+// (SPLIT true): both give the same bits.
+// Variants: WPE is the occupancy target in waves per SIMD (2: the registers of 2 waves; 4: at most
+// 128 VGPRs, so two workgroups share a CU), CH the columns per LDS chunk; the host autotuner
+// chooses WPE with CH = 64 (the same bits either way), CH = 32 is used only on request.  PULLK
+// (per-curve frequency lists) reads each column's K block while staging it.
 template <typename R, int WPE, int CH, bool FOLD32 = false, bool PULLK = false, bool SPLIT = false>
 __global__ void __launch_bounds__(kThreads, WPE)
 pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ order,
