@@ -227,7 +227,7 @@ def valu_probe():
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (--gpus %d "
               "requested)" % a.gpus, file=sys.stderr)
         sys.exit(2)
     probe = None if a.no_probe else valu_probe()
