@@ -380,16 +380,23 @@ __device__ __forceinline__ void ladd(double* p, double v) {
 // One term of the pair sums for row i of this wave and the current column j: the kernel value
 // g = exp2(-(d^2 + moff)) with d = h_s(i) h_c(j) - h_c(i) h_s(j) and moff = 0 (or +inf for a row
 // that is masked out, giving g = 0), added to a column partial T, the row sum G and a K-weighted
-// column partial J.
-template <typename R>
+// column partial J.  With FIRST the term starts the column partials instead (T = g, J = k g): the
+// same values as adding to partials of zero, since g and k are never negative, without the
+// additions of zero.
+template <typename R, bool FIRST = false>
 __device__ __forceinline__ void pair_term(R hc, R hs, R ux, R uy, R moff, R k, R& T, R& G, R& J) {
     const R pr = hc * uy;
     const R d = fma(hs, ux, -pr);
     const R a = fma(d, d, moff);
     const R g = Warp<R>::kexp(-a);
-    T += g;
     G += g;
-    J = fma(k, g, J);
+    if constexpr (FIRST) {
+        T = g;
+        J = k * g;
+    } else {
+        T += g;
+        J = fma(k, g, J);
+    }
 }
 
 // The epilogue of a (curve, slot): V_J, IP_t, V_C from the FP64 pair sums and the Gram-stage
@@ -596,9 +603,13 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
                     for (int m = 0; m < ROWS; ++m) kk[m] = kr[m];
                     const R ksj = ksb[j];
                     const double rj = rr[j];
-                    R T4[4] = {R(0), R(0), R(0), R(0)}, J4[4] = {R(0), R(0), R(0), R(0)};
+                    R T4[4], J4[4];
 #pragma unroll
-                    for (int m = 0; m < ROWS; ++m)
+                    for (int m = 0; m < 4; ++m)
+                        pair_term<R, true>(ci[m], si[m], u.x, u.y, zero, kk[m], T4[m], G[m],
+                                           J4[m]);
+#pragma unroll
+                    for (int m = 4; m < ROWS; ++m)
                         pair_term<R>(ci[m], si[m], u.x, u.y, zero, kk[m], T4[m & 3], G[m],
                                      J4[m & 3]);
                     const R Tq = (T4[0] + T4[1]) + (T4[2] + T4[3]);
@@ -619,12 +630,30 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
                     R kk[ROWS];
 #pragma unroll
                     for (int m = 0; m < ROWS; ++m) kk[m] = kr[m];
-                    R T4[4] = {R(0), R(0), R(0), R(0)}, J4[4] = {R(0), R(0), R(0), R(0)};
+                    R T4[4], J4[4];
                     // Masked rows get an exponent offset of +inf (g = 0, adding exactly nothing);
                     // groups of GRP rows that are entirely masked are skipped.  cnt and the
-                    // branches are wave-uniform.
+                    // branches are wave-uniform.  Rows 0-3 start the four partials (a skipped
+                    // group's partials start at zero).
 #pragma unroll
-                    for (int g0 = 0; g0 < ROWS; g0 += GRP) {
+                    for (int g0 = 0; g0 < 4; g0 += GRP) {
+                        if (g0 < cnt) {
+#pragma unroll
+                            for (int m = g0; m < g0 + GRP; ++m) {
+                                const R off = (m < cnt) ? zero : pinf;
+                                pair_term<R, true>(ci[m], si[m], u.x, u.y, off, kk[m], T4[m], G[m],
+                                                   J4[m]);
+                            }
+                        } else {
+#pragma unroll
+                            for (int m = g0; m < g0 + GRP; ++m) {
+                                T4[m] = zero;
+                                J4[m] = zero;
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int g0 = 4; g0 < ROWS; g0 += GRP) {
                         if (g0 < cnt) {
 #pragma unroll
                             for (int m = g0; m < g0 + GRP; ++m) {
