@@ -56,6 +56,20 @@ struct CurveParams {
     int64_t pqoff; // first piece of this curve in a one-piece-per-workgroup launch's partial sums
 };
 
+// Interleaved partial sums of a column's terms over a wave's rows (row m goes to partial
+// m mod kPartials), combined at the end of the column: the pair kernel and the column-sum tables
+// it subtracts use the same order.  Two partials issue 1% faster than four (two adds fewer per
+// column and sum) and as fast as one.
+constexpr int kPartials = 2;
+static_assert(kPartials == 1 || kPartials == 2 || kPartials == 4, "1, 2 or 4 partial sums");
+
+template <typename R>
+__host__ __device__ inline R combine_partials(const R* p) {
+    if constexpr (kPartials == 1) return p[0];
+    else if constexpr (kPartials == 2) return p[0] + p[1];
+    else return (p[0] + p[1]) + (p[2] + p[3]);
+}
+
 // Rows per wave of the pair kernel for each arithmetic type (a pass is kWaves times this).
 template <typename R>
 constexpr int rows_per_wave() {

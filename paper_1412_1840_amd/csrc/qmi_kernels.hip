@@ -237,10 +237,10 @@ gram_finalize_kernel(CurveParams* __restrict__ cp, const double* __restrict__ rd
 
 // Column K-sums in the pair kernel's own rounding order: for pass p, wave w and column j, the
 // sum over the wave's rows i < j of K(i, j), accumulated in the kernel type exactly as the pair
-// kernel accumulates K(i, j) g_ij: four interleaved partials (rows m mod 4, each row by row with
-// an fma), combined as (a0 + a1) + (a2 + a3).  Where every g_ij of a column is exactly 1
-// (coincident phases, f = 0) the kernel's column sum equals this value bit for bit, so their
-// difference is exactly zero.  One block per curve.
+// kernel accumulates K(i, j) g_ij: kPartials interleaved partials (rows m mod kPartials, each row
+// by row with an fma), combined as the kernel combines them.  Where every g_ij of a column is
+// exactly 1 (coincident phases, f = 0) the kernel's column sum equals this value bit for bit, so
+// their difference is exactly zero.  One block per curve.
 constexpr int kKsBlock = 256;
 
 template <typename R>
@@ -270,11 +270,13 @@ ksum_kernel(const CurveParams* __restrict__ cp, const R* __restrict__ K, R* __re
 #pragma unroll
         for (int q = 0; q < (int)(ROWS * sizeof(R) / 16); ++q)
             *reinterpret_cast<float4*>(&kv[q * 16 / sizeof(R)]) = kr4[q];
-        R acc[4] = {R(0), R(0), R(0), R(0)};
+        R acc[kPartials];
+#pragma unroll
+        for (int q = 0; q < kPartials; ++q) acc[q] = R(0);
 #pragma unroll
         for (int m = 0; m < ROWS; ++m)
-            if (m < cnt) acc[m & 3] = fma(kv[m], R(1), acc[m & 3]);
-        ks[P.ksoff + e] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+            if (m < cnt) acc[m % kPartials] = fma(kv[m], R(1), acc[m % kPartials]);
+        ks[P.ksoff + e] = combine_partials(acc);
     }
 }
 
@@ -399,6 +401,22 @@ __device__ __forceinline__ void pair_term(R hc, R hs, R ux, R uy, R moff, R k, R
     }
 }
 
+// Scheduling request for a straight-line column body of ROWS rows: the exp of each row placed
+// between VALU work (three VALU instructions, the exp, three more), so that the exps of a wave
+// spread over the column instead of each row's chain (multiply-adds, exp, accumulations) issuing
+// back to back.
+template <typename R, int ROWS>
+__device__ __forceinline__ void interleave_exps() {
+    if constexpr (sizeof(R) == 4) {
+#pragma unroll
+        for (int m = 0; m < ROWS; ++m) {
+            __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);  // VALU
+            __builtin_amdgcn_sched_group_barrier(0x400, 1, 0);  // transcendental
+            __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
+        }
+    }
+}
+
 // The epilogue of a (curve, slot): V_J, IP_t, V_C from the FP64 pair sums and the Gram-stage
 // constants, then QMI and nCKP (Sec. 3).
 __device__ __forceinline__ void pair_scores(const CurveParams& P, double SJ, double ST, double SC,
@@ -423,7 +441,7 @@ __device__ __forceinline__ void pair_scores(const CurveParams& P, double SJ, dou
 //   ST  = sum_{i<j} g_ij                 SJ  = sum_{i<j} K(i,j) g_ij - sum_{i<j} K(i,j)
 //   SC  = sum_{i<j} (r_i + r_j) g_ij
 // with g_ij = exp(-2 sin^2(pi f (t_i - t_j)) / sigma_t^2) and r_i = sum_k K(i,k).  A column's
-// terms over the wave's rows are summed in R in four interleaved partials (rows m mod 4) and folded
+// terms over the wave's rows are summed in R in kPartials interleaved partials and folded
 // into FP64 per column; the r-weighted sums multiply R sums by FP64 row sums.  Where all kernel
 // values are 1 (coincident phases, f = 0) every R sum is exact: the column sums of g and the row
 // sums are integers, and the K-weighted column sum equals, bit for bit, the precomputed sum of K
@@ -603,17 +621,18 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
                     for (int m = 0; m < ROWS; ++m) kk[m] = kr[m];
                     const R ksj = ksb[j];
                     const double rj = rr[j];
-                    R T4[4], J4[4];
+                    R Tp[kPartials], Jp[kPartials];
 #pragma unroll
-                    for (int m = 0; m < 4; ++m)
-                        pair_term<R, true>(ci[m], si[m], u.x, u.y, zero, kk[m], T4[m], G[m],
-                                           J4[m]);
+                    for (int m = 0; m < kPartials; ++m)
+                        pair_term<R, true>(ci[m], si[m], u.x, u.y, zero, kk[m], Tp[m], G[m],
+                                           Jp[m]);
 #pragma unroll
-                    for (int m = 4; m < ROWS; ++m)
-                        pair_term<R>(ci[m], si[m], u.x, u.y, zero, kk[m], T4[m & 3], G[m],
-                                     J4[m & 3]);
-                    const R Tq = (T4[0] + T4[1]) + (T4[2] + T4[3]);
-                    const R Jq = (J4[0] + J4[1]) + (J4[2] + J4[3]);
+                    for (int m = kPartials; m < ROWS; ++m)
+                        pair_term<R>(ci[m], si[m], u.x, u.y, zero, kk[m], Tp[m % kPartials], G[m],
+                                     Jp[m % kPartials]);
+                    interleave_exps<R, ROWS>();
+                    const R Tq = combine_partials(Tp);
+                    const R Jq = combine_partials(Jp);
                     const double Td = (double)Tq;
                     ladd(aST, Td);
                     ladd(aSJ, (double)(Jq - ksj));
@@ -630,41 +649,35 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
                     R kk[ROWS];
 #pragma unroll
                     for (int m = 0; m < ROWS; ++m) kk[m] = kr[m];
-                    R T4[4], J4[4];
+                    R Tp[kPartials], Jp[kPartials];
                     // Masked rows get an exponent offset of +inf (g = 0, adding exactly nothing);
                     // groups of GRP rows that are entirely masked are skipped.  cnt and the
-                    // branches are wave-uniform.  Rows 0-3 start the four partials (a skipped
-                    // group's partials start at zero).
+                    // branches are wave-uniform.  The first kPartials rows start the partials (a
+                    // skipped group's partials start at zero; cnt > 0, so the first group runs).
+                    static_assert(kPartials % GRP == 0 || kPartials < GRP, "group layout");
 #pragma unroll
-                    for (int g0 = 0; g0 < 4; g0 += GRP) {
+                    for (int g0 = 0; g0 < ROWS; g0 += GRP) {
                         if (g0 < cnt) {
 #pragma unroll
                             for (int m = g0; m < g0 + GRP; ++m) {
                                 const R off = (m < cnt) ? zero : pinf;
-                                pair_term<R, true>(ci[m], si[m], u.x, u.y, off, kk[m], T4[m], G[m],
-                                                   J4[m]);
+                                if (m < kPartials)
+                                    pair_term<R, true>(ci[m], si[m], u.x, u.y, off, kk[m], Tp[m],
+                                                       G[m], Jp[m]);
+                                else
+                                    pair_term<R>(ci[m], si[m], u.x, u.y, off, kk[m],
+                                                 Tp[m % kPartials], G[m], Jp[m % kPartials]);
                             }
-                        } else {
+                        } else if (g0 < kPartials) {
 #pragma unroll
-                            for (int m = g0; m < g0 + GRP; ++m) {
-                                T4[m] = zero;
-                                J4[m] = zero;
-                            }
-                        }
-                    }
-#pragma unroll
-                    for (int g0 = 4; g0 < ROWS; g0 += GRP) {
-                        if (g0 < cnt) {
-#pragma unroll
-                            for (int m = g0; m < g0 + GRP; ++m) {
-                                const R off = (m < cnt) ? zero : pinf;
-                                pair_term<R>(ci[m], si[m], u.x, u.y, off, kk[m], T4[m & 3], G[m],
-                                             J4[m & 3]);
+                            for (int m = g0; m < g0 + GRP && m < kPartials; ++m) {
+                                Tp[m] = zero;
+                                Jp[m] = zero;
                             }
                         }
                     }
-                    const R Tq = (T4[0] + T4[1]) + (T4[2] + T4[3]);
-                    const R Jq = (J4[0] + J4[1]) + (J4[2] + J4[3]);
+                    const R Tq = combine_partials(Tp);
+                    const R Jq = combine_partials(Jp);
                     const double Td = (double)Tq;
                     ladd(aST, Td);
                     ladd(aSJ, (double)(Jq - ksb[j]));

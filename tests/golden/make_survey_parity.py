@@ -1,10 +1,11 @@
 """Writes <workload>_oracle.json: the FP64 oracle's full coarse-to-fine search of the first curves
 of a workload (survey_batch: 20 000 coarse + 10 x 1000 refined frequencies on [1e-3, 10] 1/d;
 long_baseline: the same on [1e-3, 20] 1/d over a 7000-day baseline; survey_stream: 30 000 coarse +
-10 x 1000 refined on [1e-3, 10] 1/d; sigma_t = 0.3, Silverman sigma_y), for the GPU parity tests
-of the best period at full size.
+10 x 1000 refined on [1e-3, 10] 1/d; Silverman sigma_y; sigma_t = the workload's 0.3 unless a
+fourth argument gives another, which goes into <workload>_st<sigma_t>_oracle.json), for the GPU
+parity tests of the best period at full size.
 
-    python tests/golden/make_survey_parity.py [n_curves] [threads] [workload]
+    python tests/golden/make_survey_parity.py [n_curves] [threads] [workload] [sigma_t]
 
 Calls only oracle/ (and the seeded input generator).  About 35 s per survey curve on 8 cores.
 """
@@ -28,11 +29,13 @@ def main():
     threads = int(sys.argv[2]) if len(sys.argv) > 2 else 0
     workload = sys.argv[3] if len(sys.argv) > 3 else "survey_batch"
     wl = synth.WORKLOADS[workload]
+    sigma_t = float(sys.argv[4]) if len(sys.argv) > 4 else wl["sigma_t"]
     make = {"survey_batch": synth.survey_batch_curve, "long_baseline": synth.long_baseline_curve,
             "survey_stream": synth.survey_stream_curve}[workload]
     kw = dict(f_min=wl["f_min"], f_max=wl["f_max"], n_coarse=wl["n_coarse"], top_k=wl["top_k"],
               n_fine=wl["n_fine"])
-    out_path = os.path.join(HERE, "%s_oracle.json" % workload)
+    name = (workload if sigma_t == wl["sigma_t"] else "%s_st%g" % (workload, sigma_t))
+    out_path = os.path.join(HERE, "%s_oracle.json" % name)
     records = []
     if os.path.exists(out_path):
         records = json.load(open(out_path))["curves"]
@@ -42,7 +45,7 @@ def main():
             continue
         c = make(k)
         t0 = time.time()
-        r = O.best_period(c.t, c.y, c.e, wl["sigma_t"], O.SIGMA_SILVERMAN, n_threads=threads, **kw)
+        r = O.best_period(c.t, c.y, c.e, sigma_t, O.SIGMA_SILVERMAN, n_threads=threads, **kw)
         fq = np.sort(r.fine_scores.ravel())[::-1]
         cq = r.coarse_scores
         peaks = O.top_peaks(cq, kw["top_k"] + 1)
@@ -59,7 +62,7 @@ def main():
         })
         records.sort(key=lambda x: x["k"])
         with open(out_path + ".tmp", "w") as f:
-            json.dump({"workload": workload, "search": kw, "sigma_t": wl["sigma_t"],
+            json.dump({"workload": workload, "search": kw, "sigma_t": sigma_t,
                        "sigma_y": "silverman", "curves": records}, f, indent=1)
         os.replace(out_path + ".tmp", out_path)
         print("curve %d N=%d done in %.1f s" % (k, c.n, time.time() - t0), flush=True)
