@@ -263,14 +263,35 @@ int qmi_periodogram(qmi_ctx *ctx, const qmi_batch *batch, const qmi_kernel_param
 int qmi_best_period(qmi_ctx *ctx, const qmi_batch *batch, const qmi_kernel_params *kp,
                     const qmi_search *search, qmi_result *out, double *coarse_out);
 
-/* Device-pointer variants: batch->t, y, e, freqs and every output are device pointers (e.g.
- * PyTorch-owned); out stays a host array.  They run on the context's stream and return after it
- * has completed. */
+/* Device-pointer variants: batch->t, y, e, freqs, score_out, ips_out and coarse_out are device
+ * pointers (e.g. PyTorch-owned); offsets, ip_y_out, status_out and out stay host arrays.  They run
+ * on the context's stream and return after it has completed. */
 int qmi_periodogram_dev(qmi_ctx *ctx, const qmi_batch *batch, const qmi_kernel_params *kp,
                         const double *freqs, int32_t n_freq, int32_t score, double *score_out,
                         double *ips_out, double *ip_y_out, int32_t *status_out);
 int qmi_best_period_dev(qmi_ctx *ctx, const qmi_batch *batch, const qmi_kernel_params *kp,
                         const qmi_search *search, qmi_result *out, double *coarse_out);
+
+/*
+ * For callers that cannot allocate device memory during the call (code that must not call
+ * hipMalloc: tight serving loops, harnesses that forbid allocation): qmi_periodogram_dev computed
+ * in a fixed scratch area instead of the context's buffers.  Arguments, layouts and results are
+ * those of qmi_periodogram_dev (device t, y, e, freqs, score_out, ips_out; host offsets, ip_y_out,
+ * status_out), and the results are bit-identical to it.  The call allocates nothing: every
+ * intermediate table (per-curve parameters, magnitude Gram tables, row and column sums, partial
+ * sums) lives in one static device array of QMI_NOALLOC_SCRATCH_BYTES per GPU, whose address is
+ * resolved when the first context on that GPU is created and which the GPU holds until the
+ * process ends.  The whole batch must fit it at once (about N * ceil(N/256) * 256 * 4 bytes per
+ * curve of N samples, so one curve of up to ~3800 samples, or ~15 curves of 1000); a batch that
+ * does not fit returns QMI_ENOMEM before any device work, outputs untouched.  Nothing in the
+ * array needs to start at zero.  Every call on a GPU shares that GPU's array: calls that overlap
+ * on one GPU (from several contexts or threads) race and must be serialised by the caller.  No
+ * timing is recorded (qmi_get_stats reads zeros) and no hipGraph is captured.
+ */
+#define QMI_NOALLOC_SCRATCH_BYTES (64u << 20)
+int qmi_periodogram_noalloc(qmi_ctx *ctx, const qmi_batch *batch, const qmi_kernel_params *kp,
+                            const double *freqs, int32_t n_freq, int32_t score, double *score_out,
+                            double *ips_out, double *ip_y_out, int32_t *status_out);
 
 /*
  * Best period over the trial frequencies of the bands method (Sec. 3.1 followed by the score of

@@ -61,6 +61,11 @@ struct qmi_ctx {
     Buf bufs[kNumBufs];
     static_assert(kNumBufs <= 64, "one bit per buffer in in_use");
     uint64_t in_use = 0;  // bit per buffer ensured by the current operation
+    // Scratch mode (qmi_periodogram_noalloc): the current call takes its buffers from the
+    // device's static scratch array by bump allocation instead of from bufs.
+    char* ws_base = nullptr;
+    size_t ws_size = 0, ws_used = 0;
+    void* ws_ptr[kNumBufs] = {};
     // Graph cache (device section of one planned group).
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -75,7 +80,27 @@ struct qmi_ctx {
     std::mutex call_mu;  // serialises device calls between the serving thread and the caller
 };
 
+// Scratch memory of qmi_periodogram_noalloc: one static array per device, resolved once per
+// device (hipGetSymbolAddress, with that device current) when the first context on it is created.
+// In host code the array's name is only a stand-in; its device address is g_scratch[device].
+static __device__ __align__(256) unsigned char scratch[QMI_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// Resolves the device address of the scratch array on the current device (once per device).
+hipError_t resolve_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[device]) return hipSuccess;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e == hipSuccess) g_scratch[device] = p;
+    return e;
+}
 
 void set_err(qmi_ctx* ctx, const char* fmt, ...) {
     char buf[512];
@@ -158,7 +183,37 @@ int ensure(qmi_ctx* ctx, int id, size_t bytes) {
 
 template <typename T>
 T* dptr(qmi_ctx* ctx, int id) {
-    return reinterpret_cast<T*>(ctx->bufs[id].p);
+    return reinterpret_cast<T*>(ctx->ws_base ? ctx->ws_ptr[id] : ctx->bufs[id].p);
+}
+
+// A buffer of the current call: the context's own (grown on demand, see ensure), or in scratch
+// mode the next 256-byte aligned piece of the scratch array.  Scratch mode never allocates.
+int acquire(qmi_ctx* ctx, int id, size_t bytes) {
+    if (!ctx->ws_base) return ensure(ctx, id, bytes);
+    if (bytes == 0) bytes = 256;
+    const size_t at = (ctx->ws_used + 255) / 256 * 256;
+    if (at > ctx->ws_size || bytes > ctx->ws_size - at) {
+        set_err(ctx, "the call needs more than the %zu bytes of scratch memory available to "
+                "qmi_periodogram_noalloc", ctx->ws_size);
+        return QMI_ENOMEM;
+    }
+    ctx->ws_ptr[id] = ctx->ws_base + at;
+    ctx->ws_used = at + bytes;
+    return QMI_OK;
+}
+
+int scratch_for_device(qmi_ctx* ctx, void** base) {
+    void* p = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (ctx->device >= 0 && ctx->device < kMaxDevices) p = g_scratch[ctx->device];
+    }
+    if (!p) {
+        set_err(ctx, "the scratch array of device %d was not resolved", ctx->device);
+        return QMI_EDEVICE;
+    }
+    *base = p;
+    return QMI_OK;
 }
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
@@ -241,6 +296,7 @@ size_t curve_bytes(int64_t n, int64_t F1, int64_t F2, bool fp64, bool ips, bool 
 }
 
 struct CallSpec {
+    bool noalloc;          // buffers from the device's scratch array (qmi_periodogram_noalloc)
     bool dev_inputs;       // batch arrays are device pointers
     bool dev_outputs;      // score/ips/coarse outputs are device pointers
     bool periodogram;      // caller list (true) or coarse-to-fine search (false)
@@ -390,7 +446,7 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
 
     int rc;
 #define ENSURE(id, bytes) \
-    if ((rc = ensure(ctx, id, (bytes))) != QMI_OK) return rc
+    if ((rc = acquire(ctx, id, (bytes))) != QMI_OK) return rc
     if (!cs.dev_inputs) {
         ENSURE(qmi_ctx::kT, ns * 8);
         ENSURE(qmi_ctx::kY, ns * 8);
@@ -442,7 +498,7 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
     bool split2 = refine && max_pieces > 1 && nc * tiles2 < kSplitBelow;
     if ((split1 || split2) &&
         (part_bytes > kSplitMaxBytes || (size_t)part_bytes > ctx->budget / 8 ||
-         ensure(ctx, qmi_ctx::kPart, part_bytes) != QMI_OK)) {
+         acquire(ctx, qmi_ctx::kPart, part_bytes) != QMI_OK)) {
         split1 = split2 = false;
         ctx->err.clear();
     }
@@ -581,8 +637,7 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
     for (int32_t i = 0; i < nc; ++i)
         if (cp[i].status == QMI_OK) group_items += 0.5 * cp[i].n * (cp[i].n - 1.0) * (double)F1;
     const bool tune_now = !fp64 && !fold32 && ctx->tile == 0 && ctx->tuned[bucket] < 0 &&
-                          nvar > 1 &&
-                          group_items > 2e9;
+                          nvar > 1 && !ctx->ws_base && group_items > 2e9;
     ctx->stats.pair_variant = variant;
 
     // The device section: every kernel of the call, and the timing events around the pair kernels.
@@ -630,9 +685,10 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
         return QMI_OK;
     };
 
-    // Graph replay: only for a call that is one group (event indices then start at 0).
+    // Graph replay: only for a call that is one group (event indices then start at 0), and not
+    // in scratch mode (a capture and its instantiation allocate).
     bool ran = false;
-    if (ctx->use_graph && ctx->ev_used == 0) {
+    if (ctx->use_graph && ctx->ev_used == 0 && !ctx->ws_base) {
         auto u = [](const void* p) { return (uint64_t)(uintptr_t)p; };
         auto dbits = [](double v) { uint64_t b; std::memcpy(&b, &v, 8); return b; };
         std::vector<uint64_t> key = {
@@ -695,7 +751,8 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
         }
     }
     if (!ran) {
-        const int rc_sec = section(true);
+        // Scratch mode records no timing events (their creation allocates).
+        const int rc_sec = section(!ctx->ws_base);
         if (rc_sec != QMI_OK) return rc_sec;
     }
 
@@ -891,8 +948,23 @@ int run_call(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs) {
     if (b->n_curves == 0) return QMI_OK;
     HIP_OK(ctx, hipSetDevice(ctx->device));
     std::vector<Group> groups;
-    rc = plan_groups(ctx, b, cs, groups);
-    if (rc) return rc;
+    if (cs.noalloc) {
+        // The whole batch is one group, its buffers in the device's scratch array.
+        void* base = nullptr;
+        rc = scratch_for_device(ctx, &base);
+        if (rc) return rc;
+        groups.push_back(Group{0, b->n_curves, 0, b->offsets[b->n_curves]});
+        ctx->ws_base = static_cast<char*>(base);
+        ctx->ws_size = QMI_NOALLOC_SCRATCH_BYTES;
+        ctx->ws_used = 0;
+    } else {
+        rc = plan_groups(ctx, b, cs, groups);
+        if (rc) return rc;
+    }
+    struct ScratchOff {
+        qmi_ctx* c;
+        ~ScratchOff() { c->ws_base = nullptr; }
+    } scratch_off{ctx};
     ctx->ev_used = 0;
     std::vector<int32_t> pair_ev;
     for (const Group& g : groups) {
@@ -1026,6 +1098,12 @@ int qmi_create(qmi_ctx** out, int hip_device, size_t hbm_budget_bytes, void* hip
         set_err(nullptr, "hipSetDevice(%d) failed", hip_device);
         return QMI_EDEVICE;
     }
+    e = resolve_scratch(hip_device);
+    if (e != hipSuccess) {
+        set_err(nullptr, "hipGetSymbolAddress(scratch) on device %d failed: %s", hip_device,
+                hipGetErrorString(e));
+        return QMI_EDEVICE;
+    }
     std::unique_ptr<qmi_ctx> ctx(new (std::nothrow) qmi_ctx());
     if (!ctx) {
         set_err(nullptr, "out of host memory");
@@ -1145,6 +1223,31 @@ int qmi_periodogram_dev(qmi_ctx* ctx, const qmi_batch* batch, const qmi_kernel_p
                         double* ips_out, double* ip_y_out, int32_t* status_out) {
     if (!ctx) return QMI_EINVAL;
     CallSpec cs{};
+    cs.dev_inputs = true;
+    cs.dev_outputs = true;
+    cs.periodogram = true;
+    cs.kp = kp;
+    cs.freqs = freqs;
+    cs.n_freq = n_freq;
+    cs.score = score;
+    cs.score_out = score_out;
+    cs.ips_out = ips_out;
+    cs.ip_y_out = ip_y_out;
+    cs.status_out = status_out;
+    try {
+        return run_call(ctx, batch, cs);
+    } catch (...) {
+        set_err(ctx, "internal exception");
+        return QMI_EINTERNAL;
+    }
+}
+
+int qmi_periodogram_noalloc(qmi_ctx* ctx, const qmi_batch* batch, const qmi_kernel_params* kp,
+                            const double* freqs, int32_t n_freq, int32_t score, double* score_out,
+                            double* ips_out, double* ip_y_out, int32_t* status_out) {
+    if (!ctx) return QMI_EINVAL;
+    CallSpec cs{};
+    cs.noalloc = true;
     cs.dev_inputs = true;
     cs.dev_outputs = true;
     cs.periodogram = true;

@@ -39,9 +39,11 @@ MAX_TOPK = 32
 MAX_BANDS = 32
 MAX_TRIALS = 1024
 MAX_MASKS = 32
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 SYMBOLS = ("qmi_create", "qmi_destroy", "qmi_last_error", "qmi_set_option", "qmi_get_stats",
            "qmi_periodogram", "qmi_best_period", "qmi_periodogram_dev", "qmi_best_period_dev",
+           "qmi_periodogram_noalloc",
            "qmi_discriminate", "qmi_calibrate", "qmi_serve_start", "qmi_submit", "qmi_poll",
            "qmi_serve_stop", "qmi_bands_best_period", "qmi_preprocess", "qmi_whiten",
            "qmi_set_masks")
@@ -148,7 +150,7 @@ def lib() -> ctypes.CDLL:
         L.qmi_get_stats.argtypes = [V, P(Stats)]
         L.qmi_set_masks.argtypes = [V, V, I32]
         L.qmi_set_masks.restype = ctypes.c_int
-        for name in ("qmi_periodogram", "qmi_periodogram_dev"):
+        for name in ("qmi_periodogram", "qmi_periodogram_dev", "qmi_periodogram_noalloc"):
             f = getattr(L, name)
             f.argtypes = [V, P(Batch), P(KernelParams), V, I32, I32, V, V, V, V]
             f.restype = ctypes.c_int
@@ -387,6 +389,21 @@ class Context:
                                               _addr(freqs), int(freqs.numel()), int(score),
                                               _addr(score_out), _addr(ips_out), ipy.ctypes.data,
                                               st.ctypes.data))
+        return ipy, st
+
+    def periodogram_noalloc(self, offsets, t, y, e, freqs, score_out, sigma_t: float,
+                            sigma_y: float = SIGMA_SILVERMAN, score: int = SCORE_QMI,
+                            precision: int = PREC_MIXED, ips_out=None):
+        """periodogram_dev computed in the library's fixed scratch area (no device allocation
+        during the call; at most NOALLOC_SCRATCH_BYTES of intermediate tables)."""
+        b, off = self._batch(offsets, t, y, e)
+        ipy = np.empty(b.n_curves)
+        st = np.empty(b.n_curves, np.int32)
+        kp = kernel_params(sigma_t, sigma_y, precision)
+        self._check(lib().qmi_periodogram_noalloc(self._h, ctypes.byref(b), ctypes.byref(kp),
+                                                  _addr(freqs), int(freqs.numel()), int(score),
+                                                  _addr(score_out), _addr(ips_out),
+                                                  ipy.ctypes.data, st.ctypes.data))
         return ipy, st
 
     def best_period_dev(self, offsets, t, y, e, sigma_t: float, f_min: float, f_max: float,

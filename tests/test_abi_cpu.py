@@ -47,6 +47,8 @@ def test_header_constants_match_binding():
     assert val("QMI_MAX_BANDS") == qmi.MAX_BANDS and val("QMI_MAX_TRIALS") == qmi.MAX_TRIALS
     assert val("QMI_MAX_MASKS") == qmi.MAX_MASKS
     assert val("QMI_PREC_FOLD32") == qmi.PREC_FOLD32
+    m = re.search(r"#define\s+QMI_NOALLOC_SCRATCH_BYTES\s+\((\d+)u << (\d+)\)", text)
+    assert (int(m.group(1)) << int(m.group(2))) == qmi.NOALLOC_SCRATCH_BYTES
 
 
 def test_struct_sizes():
