@@ -17,6 +17,8 @@ separately):
 * sigma_y defaults to Silverman's rule 0.9 min(s, IQR/1.34) N^(-1/5) with s on N-1 and
   linear-interpolation quartiles; IQR = 0 falls back to s; s = 0 is degenerate.  The paper's own
   rule sigma_y = median(error bars) (Sec. 3) is the alternative;
+* sigma_t is a caller value, or the skewness rule of Sec. 3 with the quartiles of its footnote
+  (halves without the middle value for odd N) and S = 0 when Q3 = Q1;
 * peaks of the coarse periodogram are its local maxima (q_k > q_{k-1} and q_k >= q_{k+1}; the first
   point needs q_0 >= q_1, the last q_{F-1} > q_{F-2}), ranked by value with ties to lower k;
 * each kept peak k is refined on n_fine evenly spaced points of [f_{k-1}, f_{k+1}] (clamped to the
@@ -136,6 +138,55 @@ def sigma_y_of(y: np.ndarray, e: Optional[np.ndarray], rule: float) -> float:
             raise Degenerate("median error bar is not positive")
         return m
     raise ValueError("unknown sigma_y rule %r" % rule)
+
+
+# ------------------------------------------------------------------------------------------
+# sigma_t from the skewness of the magnitudes (Sec. 3, the skewness rule and its quartile
+# estimator of the skewness; in the paper's source text this passage is commented out, while the
+# published text and the caption of its sigma_t example figure still describe the per-curve choice)
+# ------------------------------------------------------------------------------------------
+
+SIGMA_T_SKEWNESS = -1.0
+SKEW_LAMBDA = 0.1  # the constants the paper reports for EROS-2
+SKEW_MU = 12.0
+
+
+def hinge_quartiles(x: np.ndarray) -> Tuple[float, float, float]:
+    """Q1, Q2, Q3 as the paper's footnote defines them: Q2 is the median, Q1 and Q3 the medians of
+    the first and second half of the rank-ordered values.  For odd N the middle value belongs to
+    neither half (the halves are the N // 2 lowest and the N // 2 highest values)."""
+    s = sorted(float(v) for v in x)
+    n = len(s)
+    h = n // 2
+    if h == 0:
+        return s[0], s[0], s[0]
+    return median(s[:h]), median(s), median(s[n - h:])
+
+
+def bowley_skewness(x: np.ndarray) -> float:
+    """Quartile estimator of the skewness S = (Q3 + Q1 - 2 Q2) / (Q3 - Q1), in [-1, 1]; 0 when
+    Q3 = Q1 (no spread between the quartiles; the estimator is then 0 / 0)."""
+    q1, q2, q3 = hinge_quartiles(x)
+    if q3 == q1:
+        return 0.0
+    return (q3 + q1 - 2.0 * q2) / (q3 - q1)
+
+
+def sigma_t_skewness(y: np.ndarray, lam: float = SKEW_LAMBDA, mu: float = SKEW_MU) -> float:
+    """sigma_t = lambda + 0.5 exp(-mu S^2): about lambda + 0.5 for symmetric magnitude
+    distributions, down to lambda for very skewed ones (eclipsing binaries)."""
+    S = bowley_skewness(y)
+    return lam + 0.5 * math.exp(-mu * S * S)
+
+
+def sigma_t_of(y: np.ndarray, sigma_t: float, lam: float = SKEW_LAMBDA,
+               mu: float = SKEW_MU) -> float:
+    """sigma_t > 0 explicit; SIGMA_T_SKEWNESS the skewness rule."""
+    if sigma_t > 0:
+        return float(sigma_t)
+    if sigma_t == SIGMA_T_SKEWNESS:
+        return sigma_t_skewness(y, lam, mu)
+    raise ValueError("unknown sigma_t rule %r" % sigma_t)
 
 
 # ------------------------------------------------------------------------------------------
@@ -332,6 +383,7 @@ def best_period(t, y, e, sigma_t: float, sigma_y_rule: float, f_min: float, f_ma
     t = np.asarray(t, np.float64)
     y = np.asarray(y, np.float64)
     sy = sigma_y_of(y, None if e is None else np.asarray(e, np.float64), sigma_y_rule)
+    sigma_t = sigma_t_of(y, sigma_t)
     grid = linear_grid(f_min, f_max, n_coarse)
     ips = information_potentials(t, y, sigma_t, sy, grid, mode, n_threads)
     q = score_of(ips, score)
@@ -531,6 +583,7 @@ def bands_best_period(t, y, e, sigma_t: float, sigma_y_rule: float, n_keep: int 
     f = tr["freqs"]
     sy = sigma_y_of(np.asarray(y, np.float64), None if e is None else np.asarray(e, np.float64),
                     sigma_y_rule)
+    sigma_t = sigma_t_of(np.asarray(y, np.float64), sigma_t)
     if len(f) == 0:
         return dict(tr, scores=np.zeros(0), best=-1, f_best=math.nan, score=math.nan, sigma_y=sy)
     ips = information_potentials(t, y, sigma_t, sy, f, 1, n_threads)
