@@ -97,13 +97,28 @@ typedef struct {
     const double *e; /* error bars, nullable (needed by QMI_SIGMA_MEDIAN_ERR and for pSNR) */
 } qmi_batch;
 
-/* sigma_t > 0: periodic-kernel width (Sec. 3 finds 0.1 - 0.6 typical).  sigma_y > 0: explicit
- * magnitude-kernel width, or one of the QMI_SIGMA_* rules.  precision: QMI_PREC_*. */
+/* sigma_t rule (qmi_kernel_params.sigma_t == QMI_SIGMA_T_SKEWNESS): per curve,
+ * sigma_t = skew_lambda + 0.5 exp(-skew_mu S^2), S = (Q3 + Q1 - 2 Q2) / (Q3 - Q1) the quartile
+ * estimator of the skewness of the magnitudes (Sec. 3, the skewness rule; S = 0 when Q3 = Q1), with
+ * Q2 the median and Q1, Q3 the medians of the lower and upper half of the sorted magnitudes (for
+ * odd N the middle value belongs to neither half).  Symmetric distributions get about
+ * skew_lambda + 0.5, very skewed ones (eclipses) about skew_lambda.  The paper reports
+ * skew_lambda = 0.1 and skew_mu = 12 for its survey; both zero selects these. */
+#define QMI_SIGMA_T_SKEWNESS (-1.0)
+#define QMI_SKEW_LAMBDA 0.1
+#define QMI_SKEW_MU 12.0
+
+/* sigma_t > 0: periodic-kernel width (Sec. 3 finds 0.1 - 0.6 typical), or QMI_SIGMA_T_SKEWNESS.
+ * sigma_y > 0: explicit magnitude-kernel width, or one of the QMI_SIGMA_* rules.  precision:
+ * QMI_PREC_*.  skew_lambda > 0 and skew_mu >= 0: constants of the sigma_t rule (both 0: the
+ * paper's), read only when the rule is selected. */
 typedef struct {
     double sigma_t;
     double sigma_y;
     int32_t precision;
     int32_t reserved;
+    double skew_lambda;
+    double skew_mu;
 } qmi_kernel_params;
 
 /*
@@ -178,6 +193,7 @@ typedef struct {
     int32_t n;             /* samples */
     int32_t status;        /* QMI_OK or the per-curve QMI_E* code */
     int32_t reserved;
+    double sigma_t;        /* periodic-kernel width used */
 } qmi_result;
 
 /* SNR-binned thresholds (Sec. 4.1): bin b is [edges[b], edges[b+1]); periodic iff score > th[b]. */

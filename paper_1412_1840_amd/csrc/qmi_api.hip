@@ -220,8 +220,17 @@ inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 int check_kernel_params(qmi_ctx* ctx, const qmi_kernel_params* kp) {
     if (!kp) { set_err(ctx, "kernel params is NULL"); return QMI_EINVAL; }
-    if (!(kp->sigma_t > 0.0) || !std::isfinite(kp->sigma_t)) {
-        set_err(ctx, "sigma_t must be finite and > 0 (got %g)", kp->sigma_t);
+    if ((!(kp->sigma_t > 0.0) || !std::isfinite(kp->sigma_t)) &&
+        kp->sigma_t != QMI_SIGMA_T_SKEWNESS) {
+        set_err(ctx, "sigma_t must be finite and > 0 or QMI_SIGMA_T_SKEWNESS (got %g)",
+                kp->sigma_t);
+        return QMI_EINVAL;
+    }
+    if (kp->sigma_t == QMI_SIGMA_T_SKEWNESS && !(kp->skew_lambda == 0.0 && kp->skew_mu == 0.0) &&
+        !(kp->skew_lambda > 0.0 && std::isfinite(kp->skew_lambda) && kp->skew_mu >= 0.0 &&
+          std::isfinite(kp->skew_mu))) {
+        set_err(ctx, "the sigma_t rule needs skew_lambda > 0 and skew_mu >= 0 (got %g, %g)",
+                kp->skew_lambda, kp->skew_mu);
         return QMI_EINVAL;
     }
     if (!(kp->sigma_y > 0.0 && std::isfinite(kp->sigma_y)) && kp->sigma_y != QMI_SIGMA_SILVERMAN &&
@@ -640,6 +649,10 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
                           nvar > 1 && !ctx->ws_base && group_items > 2e9;
     ctx->stats.pair_variant = variant;
 
+    const bool skew_default = kp->skew_lambda == 0.0 && kp->skew_mu == 0.0;
+    const double skew_lambda = skew_default ? QMI_SKEW_LAMBDA : kp->skew_lambda;
+    const double skew_mu = skew_default ? QMI_SKEW_MU : kp->skew_mu;
+
     // The device section: every kernel of the call, and the timing events around the pair kernels.
     // It contains no copies or allocations, so it can be captured into a hipGraph and replayed.
     auto section = [&](bool events) -> int {
@@ -647,7 +660,7 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
             if (events) record(ctx);
         };
         rec();  // device section start
-        HIP_OK(ctx, launch_prologue(st, dcp, nc, max_n, t, y, e));
+        HIP_OK(ctx, launch_prologue(st, dcp, nc, max_n, t, y, e, skew_lambda, skew_mu));
         HIP_OK(ctx, launch_gram<R>(st, dcp, nc, rows, drow, y, K, rp, rd));
         HIP_OK(ctx, launch_gram_finalize<R>(st, dcp, nc, rd, rp));
         HIP_OK(ctx, launch_ksum<R>(st, dcp, nc, K, ks));
@@ -694,7 +707,8 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
         std::vector<uint64_t> key = {
             (uint64_t)fp64, (uint64_t)cs.periodogram, (uint64_t)nc, (uint64_t)rows,
             (uint64_t)max_n, (uint64_t)F1, (uint64_t)F2, (uint64_t)top_k, (uint64_t)n_fine,
-            (uint64_t)score_kind, (uint64_t)variant, dbits(fp.f0), dbits(fp.df), u(st), u(t), u(y),
+            (uint64_t)score_kind, (uint64_t)variant, dbits(fp.f0), dbits(fp.df),
+            dbits(skew_lambda), dbits(skew_mu), u(st), u(t), u(y),
             u(e), u(dcp),
             u(dorder), u(drow), u(K), u(rp), u(rd), u(ks), u(dfreqs), u(coarse), u(coarse2),
             u(po.ips), u(fine), u(fine2), u(pk.peak_k), u(pk.npk), u(pk.win), u(pk.argmax),
@@ -824,6 +838,7 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
                 rr.status = cp[i].status;
                 rr.n = cp[i].n;
             }
+            if (cp[i].status != QMI_OK) rr.sigma_t = NAN;
             if (rr.status != QMI_OK) {
                 rr.f_best = rr.period = rr.score = rr.score_qmi = rr.score_nckp = NAN;
                 rr.coarse_best = NAN;

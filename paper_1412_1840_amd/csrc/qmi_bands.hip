@@ -417,6 +417,7 @@ bands_best_kernel(const CurveParams* __restrict__ cp, const double* __restrict__
     if (threadIdx.x != 0) return;
     DevResult r;
     r.sigma_y = P.sigma_y;
+    r.sigma_t = P.sigma_t > 0.0 ? P.sigma_t : NAN;  // the rule flag until the prologue ran
     r.psnr = P.psnr;
     r.coarse_best = NAN;
     r.n = P.n;

@@ -44,7 +44,7 @@ struct CurveParams {
     int32_t npad;  // K-table row length (multiple of kPass)
     int32_t status;
     int32_t has_e;
-    double sigma_t;
+    double sigma_t;       // > 0; QMI_SIGMA_T_SKEWNESS until the prologue sets it
     double sigma_y_rule;  // > 0 explicit, -1 Silverman, -2 median error bar
     double sigma_y;
     double A, B;   // 1 / (sqrt(2 pi) sigma)
@@ -130,6 +130,7 @@ __device__ __forceinline__ bool in_mask(const MaskDev& md, double f, double s) {
 struct DevResult {
     double f_best, period, score, score_qmi, score_nckp, sigma_y, psnr, coarse_best;
     int32_t coarse_index, peak_rank, fine_index, coarse_argmax, n_peaks, n, status, reserved;
+    double sigma_t;
 };
 
 // Bands method (qmi_bands.hip): per-group device buffers and parameters.
@@ -173,8 +174,11 @@ hipError_t launch_whiten(hipStream_t st, int n_curves, int max_n, const int64_t*
                          const int32_t* status, double* y_out);
 
 // Launchers (qmi_kernels.hip).  All launch on `st` and return hipGetLastError().
+// skew_lambda, skew_mu: constants of the sigma_t rule, applied to curves whose sigma_t is
+// QMI_SIGMA_T_SKEWNESS.
 hipError_t launch_prologue(hipStream_t st, CurveParams* cp, int n_curves, int max_n,
-                           const double* t, const double* y, const double* e);
+                           const double* t, const double* y, const double* e, double skew_lambda,
+                           double skew_mu);
 template <typename R>
 hipError_t launch_gram(hipStream_t st, CurveParams* cp, int n_curves, int64_t total_rows,
                        const int64_t* row_curve_start, const double* y, R* K, double* rp,

@@ -89,14 +89,16 @@ __device__ double sorted_median(const double* a, int n) {
 }
 
 // --------------------------------------------------------------------------------------------
-// Prologue: validity, sigma_y (Silverman or median error bar), pSNR, A, B.  One block per curve.
+// Prologue: validity, sigma_y (Silverman or median error bar), sigma_t (given, or the skewness
+// rule of Sec. 3), pSNR, A, B.  One block per curve.
 // --------------------------------------------------------------------------------------------
 
 constexpr int kPrologueBlock = 256;
 
 __global__ void __launch_bounds__(kPrologueBlock)
 prologue_kernel(CurveParams* __restrict__ cp, const double* __restrict__ t,
-                const double* __restrict__ y, const double* __restrict__ e) {
+                const double* __restrict__ y, const double* __restrict__ e, double skew_lambda,
+                double skew_mu) {
     extern __shared__ double sbuf[];  // [QMI_MAX_N rounded to pow2] + 64 scratch
     __shared__ double red[kPrologueBlock / 64 + 1];
     __shared__ int bad;
@@ -133,6 +135,16 @@ prologue_kernel(CurveParams* __restrict__ cp, const double* __restrict__ t,
     for (int i = threadIdx.x; i < n; i += kPrologueBlock) sbuf[i] = yc[i];
     block_sort<kPrologueBlock>(sbuf, n);
     const double iqr = sorted_quantile(sbuf, n, 0.75) - sorted_quantile(sbuf, n, 0.25);
+    // sigma_t rule (Sec. 3): S = (Q3 + Q1 - 2 Q2) / (Q3 - Q1) with Q2 the median and Q1, Q3 the
+    // medians of the lower and upper n / 2 sorted magnitudes; S = 0 when Q3 = Q1.
+    double sigma_t = P.sigma_t;
+    if (!(sigma_t > 0.0)) {
+        const int h = n / 2;
+        const double q1 = sorted_median(sbuf, h), q2 = sorted_median(sbuf, n);
+        const double q3 = sorted_median(sbuf + (n - h), h);
+        const double S = (q3 == q1) ? 0.0 : (q3 + q1 - 2.0 * q2) / (q3 - q1);
+        sigma_t = skew_lambda + 0.5 * exp(-skew_mu * S * S);
+    }
     __syncthreads();
     double med_e = NAN;
     if (ec) {
@@ -158,7 +170,8 @@ prologue_kernel(CurveParams* __restrict__ cp, const double* __restrict__ t,
     }
     cp[c].status = status;
     cp[c].sigma_y = status ? NAN : sy;
-    cp[c].A = kInvSqrt2Pi / P.sigma_t;
+    cp[c].sigma_t = sigma_t;
+    cp[c].A = kInvSqrt2Pi / sigma_t;
     cp[c].B = status ? NAN : kInvSqrt2Pi / sy;
     cp[c].psnr = (ec && med_e > 0.0) ? 0.7413 * iqr / med_e : NAN;
 }
@@ -773,12 +786,13 @@ pair_epilogue_kernel(const CurveParams* __restrict__ cp, const int32_t* __restri
 // --------------------------------------------------------------------------------------------
 
 hipError_t launch_prologue(hipStream_t st, CurveParams* cp, int n_curves, int max_n,
-                           const double* t, const double* y, const double* e) {
+                           const double* t, const double* y, const double* e, double skew_lambda,
+                           double skew_mu) {
     if (n_curves <= 0) return hipSuccess;
     int m = 1;
     while (m < max_n) m <<= 1;
     size_t shm = sizeof(double) * (size_t)m;
-    prologue_kernel<<<n_curves, kPrologueBlock, shm, st>>>(cp, t, y, e);
+    prologue_kernel<<<n_curves, kPrologueBlock, shm, st>>>(cp, t, y, e, skew_lambda, skew_mu);
     return hipGetLastError();
 }
 

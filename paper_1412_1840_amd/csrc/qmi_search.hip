@@ -208,6 +208,7 @@ best_kernel(const CurveParams* __restrict__ cp, const double* __restrict__ coars
     if (threadIdx.x != 0) return;
     DevResult r;
     r.sigma_y = P.sigma_y;
+    r.sigma_t = P.sigma_t > 0.0 ? P.sigma_t : NAN;  // the rule flag until the prologue ran
     r.psnr = P.psnr;
     r.n = P.n;
     r.status = P.status;

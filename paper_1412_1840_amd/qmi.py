@@ -26,6 +26,9 @@ EINTERNAL = -6
 
 SIGMA_SILVERMAN = -1.0
 SIGMA_MEDIAN_ERR = -2.0
+SIGMA_T_SKEWNESS = -1.0
+SKEW_LAMBDA = 0.1
+SKEW_MU = 12.0
 SCORE_QMI = 0
 SCORE_NCKP = 1
 PREC_MIXED = 0
@@ -63,7 +66,8 @@ class Batch(ctypes.Structure):
 
 class KernelParams(ctypes.Structure):
     _fields_ = [("sigma_t", ctypes.c_double), ("sigma_y", ctypes.c_double),
-                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("skew_lambda", ctypes.c_double), ("skew_mu", ctypes.c_double)]
 
 
 class Search(ctypes.Structure):
@@ -118,8 +122,9 @@ RESULT_DTYPE = np.dtype([("f_best", "f8"), ("period", "f8"), ("score", "f8"), ("
                          ("score_nckp", "f8"), ("sigma_y", "f8"), ("psnr", "f8"),
                          ("coarse_best", "f8"), ("coarse_index", "i4"), ("peak_rank", "i4"),
                          ("fine_index", "i4"), ("coarse_argmax", "i4"), ("n_peaks", "i4"),
-                         ("n", "i4"), ("status", "i4"), ("reserved", "i4")])
-assert RESULT_DTYPE.itemsize == 96
+                         ("n", "i4"), ("status", "i4"), ("reserved", "i4"),
+                         ("sigma_t", "f8")])
+assert RESULT_DTYPE.itemsize == 104
 
 _LIB = None
 
@@ -189,8 +194,11 @@ def _f64(a) -> np.ndarray:
 
 
 def kernel_params(sigma_t: float, sigma_y: float = SIGMA_SILVERMAN,
-                  precision: int = PREC_MIXED) -> KernelParams:
-    return KernelParams(float(sigma_t), float(sigma_y), int(precision), 0)
+                  precision: int = PREC_MIXED, skew_lambda: float = SKEW_LAMBDA,
+                  skew_mu: float = SKEW_MU) -> KernelParams:
+    """sigma_t > 0 explicit, or SIGMA_T_SKEWNESS with the rule's constants."""
+    return KernelParams(float(sigma_t), float(sigma_y), int(precision), 0, float(skew_lambda),
+                        float(skew_mu))
 
 
 def search(f_min: float, f_max: float, n_coarse: int, top_k: int = 10, n_fine: int = 1000,

@@ -47,6 +47,8 @@ def test_header_constants_match_binding():
     assert val("QMI_MAX_BANDS") == qmi.MAX_BANDS and val("QMI_MAX_TRIALS") == qmi.MAX_TRIALS
     assert val("QMI_MAX_MASKS") == qmi.MAX_MASKS
     assert val("QMI_PREC_FOLD32") == qmi.PREC_FOLD32
+    assert val("QMI_SIGMA_T_SKEWNESS") == qmi.SIGMA_T_SKEWNESS
+    assert val("QMI_SKEW_LAMBDA") == qmi.SKEW_LAMBDA and val("QMI_SKEW_MU") == qmi.SKEW_MU
     m = re.search(r"#define\s+QMI_NOALLOC_SCRATCH_BYTES\s+\((\d+)u << (\d+)\)", text)
     assert (int(m.group(1)) << int(m.group(2))) == qmi.NOALLOC_SCRATCH_BYTES
 
@@ -54,13 +56,13 @@ def test_header_constants_match_binding():
 def test_struct_sizes():
     assert ctypes.sizeof(qmi.Stats) == 40
     assert ctypes.sizeof(qmi.Batch) == 40
-    assert ctypes.sizeof(qmi.KernelParams) == 24
+    assert ctypes.sizeof(qmi.KernelParams) == 40
     assert ctypes.sizeof(qmi.Search) == 32
     assert ctypes.sizeof(qmi.Thresholds) == 24
     assert ctypes.sizeof(qmi.Bands) == 40
     assert ctypes.sizeof(qmi.PreprocessParams) == 16
     assert ctypes.sizeof(qmi.Mask) == 24
-    assert qmi.RESULT_DTYPE.itemsize == 96
+    assert qmi.RESULT_DTYPE.itemsize == 104
 
 
 def test_discriminate_matches_oracle_rule():

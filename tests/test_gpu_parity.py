@@ -146,7 +146,7 @@ def test_call_level_errors_leave_outputs_untouched(ctx):
     c = synth.survey_batch_curve(1, n=50)
     b = pack([c])
     out = np.full((1, 3), 7.0)
-    kp = qmi.kernel_params(-1.0)  # sigma_t <= 0
+    kp = qmi.kernel_params(-0.5)  # sigma_t <= 0 and not a rule
     bb, off = ctx._batch(b.offsets, b.t, b.y, b.e)
     f = np.array([0.1, 0.2, 0.3])
     rc = qmi.lib().qmi_periodogram(ctx._h, bb, kp, f.ctypes.data, 3, 0, out.ctypes.data, None,

@@ -1,0 +1,73 @@
+"""The sigma_t skewness rule (Sec. 3) on the GPU against the oracle: on a batch of survey curves
+whose magnitude distributions range from symmetric (sinusoids, noise) to strongly skewed
+(eclipses), each curve's sigma_t, its periodogram and its coarse-to-fine search result."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1412_1840_amd import qmi, synth
+
+pytestmark = pytest.mark.gpu
+
+QMI_TOL = 1e-4
+V_RTOL = 2e-6
+
+
+def floor_rel(got, ref):
+    den = np.maximum(np.abs(ref), 1e-3 * np.max(np.abs(ref)))
+    return np.abs(np.asarray(got) - ref) / den
+
+
+def _curves():
+    # the first 40 curves of the survey batch at ragged lengths: sinusoids, sawtooths, two-dip
+    # eclipses and red noise
+    return [synth.survey_batch_curve(k, n=n)
+            for k, n in zip(range(40), [60 + 23 * (k % 17) for k in range(40)])]
+
+
+def test_per_curve_sigma_t_and_periodogram():
+    curves = _curves()
+    st_ref = np.array([O.sigma_t_skewness(c.y) for c in curves])
+    assert st_ref.max() - st_ref.min() > 0.2  # the rule gives the batch different widths
+    b = synth.pack(curves)
+    freqs = np.concatenate([[0.0], O.linear_grid(1e-3, 10.0, 299)])
+    with qmi.Context(0) as ctx:
+        sc, ips, ipy, status = ctx.periodogram(b.offsets, b.t, b.y, b.e, freqs,
+                                               qmi.SIGMA_T_SKEWNESS, want_ips=True)
+    assert np.all(status == 0)
+    refs = O.batch_information_potentials([c.t for c in curves], [c.y for c in curves], st_ref,
+                                          [O.silverman_sigma(c.y) for c in curves],
+                                          [freqs] * len(curves))
+    for k, ref in enumerate(refs):
+        assert floor_rel(sc[k], O.qmi(ref)).max() <= QMI_TOL, k
+        for q, r in enumerate((ref.vj, ref.ipt, ref.vc)):
+            np.testing.assert_allclose(ips[k, :, q], r, rtol=V_RTOL)
+        assert abs(sc[k, 0]) < 1e-12
+
+
+def test_search_reports_the_rule_width_and_matches_the_oracle():
+    curves = _curves()[:12]
+    b = synth.pack(curves)
+    kw = dict(f_min=1e-3, f_max=5.0, n_coarse=900, top_k=3, n_fine=64)
+    with qmi.Context(0) as ctx:
+        res, coarse = ctx.best_period(b.offsets, b.t, b.y, b.e, qmi.SIGMA_T_SKEWNESS,
+                                      want_coarse=True, **kw)
+        kp = qmi.kernel_params(qmi.SIGMA_T_SKEWNESS, skew_lambda=0.05, skew_mu=4.0)
+        bb, off = ctx._batch(b.offsets, b.t, b.y, b.e)
+        s = qmi.search(**kw)
+        res2 = np.zeros(b.n_curves, qmi.RESULT_DTYPE)
+        rc = qmi.lib().qmi_best_period(ctx._h, bb, kp, s, res2.ctypes.data, None)
+        assert rc == qmi.OK
+        bad = qmi.kernel_params(qmi.SIGMA_T_SKEWNESS, skew_lambda=-0.1, skew_mu=4.0)
+        rc = qmi.lib().qmi_best_period(ctx._h, bb, bad, s, res2.ctypes.data, None)
+        assert rc == qmi.EINVAL
+    for k, c in enumerate(curves):
+        st = O.sigma_t_skewness(c.y)
+        assert res["sigma_t"][k] == pytest.approx(st, rel=1e-14)
+        assert res2["sigma_t"][k] == pytest.approx(O.sigma_t_skewness(c.y, 0.05, 4.0), rel=1e-14)
+        ref = O.best_period(c.t, c.y, c.e, O.SIGMA_T_SKEWNESS, O.SIGMA_SILVERMAN, **kw)
+        assert floor_rel(coarse[k], ref.coarse_scores).max() <= QMI_TOL
+        assert res["coarse_argmax"][k] == ref.coarse_argmax, k
+        assert (res["coarse_index"][k], res["fine_index"][k]) == (ref.coarse_index,
+                                                                  ref.fine_index), k
+        assert res["score_nckp"][k] == pytest.approx(ref.nckp, rel=1e-4)
