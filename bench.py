@@ -9,6 +9,7 @@ seeded survey-like lightcurves (N uniform in 300..1000, half periodic).  Prints 
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -47,15 +48,17 @@ def parse():
     ap.add_argument("--cpu-freqs", type=int, default=4096,
                     help="coarse frequencies of the CPU-oracle sample (about 10 s on 16 cores)")
     ap.add_argument("--no-probe", action="store_true", help="skip the VALU rate probe")
-    ap.add_argument("--serve-requests", type=int, default=2000,
-                    help="requests of the serving measurement (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=5000,
+                    help="measured requests per serving load (0: skip)")
     ap.add_argument("--serve-load", type=float, default=0.5,
                     help="Poisson arrival rate as a fraction of the measured batch throughput")
     ap.add_argument("--serve-batch", type=int, default=256)
-    ap.add_argument("--serve-inflight", type=int, default=2)
-    ap.add_argument("--serve-sweep", default="",
+    ap.add_argument("--serve-inflight", type=int, default=4)
+    ap.add_argument("--serve-items", type=float, default=1e10,
+                    help="pair x frequency items per serving launch (0: no bound)")
+    ap.add_argument("--serve-sweep", default="0.25,0.5,0.8",
                     help="comma-separated loads (fractions of the saturated serving throughput, "
-                         "measured first); replaces --serve-load")
+                         "measured first; empty: one load, --serve-load of the batch rate)")
     ap.add_argument("--serve-warmup", type=int, default=500,
                     help="requests served first and left out of the latency statistics")
     ap.add_argument("--tile", type=int, default=0,
@@ -67,10 +70,20 @@ def parse():
                     help="timed steps of the same search with every curve at N = 600 (0: skip)")
     ap.add_argument("--bands-steps", type=int, default=2,
                     help="timed calls of the bands-method front end on the same batch (0: skip)")
+    ap.add_argument("--precision", type=int, default=1,
+                    help="compare the mixed and FP64 paths with the stored FP64 oracle values of "
+                         "16 long-baseline curves (0: skip)")
+    ap.add_argument("--length-sweep", default="",
+                    help="comma-separated curve lengths: print the pair kernel's rate per length "
+                         "(survey-batch generator at fixed N, 20 000 + 10 x 1000 frequencies) as "
+                         "JSON lines and exit")
+    ap.add_argument("--survey-curves", type=int, default=16384,
+                    help="survey-stream curves timed in batches of 2048 with host inputs (0: skip)")
     return ap.parse_args()
 
 
-def serving(qmi, synth, wl, st_, rate, n_req, max_batch, inflight, warmup=0, curves=None):
+def serving(qmi, synth, wl, st_, rate, n_req, max_batch, inflight, warmup=0, curves=None,
+            max_items=0):
     """Poisson stream of single-curve requests (serving-stream lengths, survey mix and search)
     into the continuous-batching loop; latency = completion (poll) - arrival, host clock.
     rate = inf submits every request at once (saturated throughput).  The first ``warmup``
@@ -84,7 +97,8 @@ def serving(qmi, synth, wl, st_, rate, n_req, max_batch, inflight, warmup=0, cur
     ctx = qmi.Context(0)
     kw = dict(f_min=wl["f_min"], f_max=wl["f_max"], n_coarse=wl["n_coarse"], top_k=wl["top_k"],
               n_fine=wl["n_fine"])
-    ctx.serve_start(st_, max_batch=max_batch, max_inflight=inflight, **kw)
+    ctx.serve_start(st_, max_batch=max_batch, max_inflight=inflight, max_batch_items=max_items,
+                    **kw)
     t_arr = np.zeros(n_req)
     t_done = np.full(n_req, np.nan)
     status = np.zeros(n_req, np.int32)
@@ -130,7 +144,7 @@ def serving(qmi, synth, wl, st_, rate, n_req, max_batch, inflight, warmup=0, cur
             "p50_ms": float(np.percentile(lat[ok], 50)),
             "p99_ms": float(np.percentile(lat[ok], 99)),
             "max_ms": float(np.max(lat[ok])), "throughput_per_s": float(ok.sum() / span),
-            "max_batch": max_batch, "max_inflight": inflight,
+            "max_batch": max_batch, "max_inflight": inflight, "max_batch_items": max_items,
             "lengths": "round(lognormal(ln 500, 0.5)) in [50, 2000]",
             "bad_status": int(np.sum(status != 0))}
 
@@ -230,6 +244,108 @@ def valu_probe():
         return None
 
 
+def precision_report(qmi, synth):
+    """The mixed and FP64 paths against stored FP64 oracle values (tests/golden/
+    long_baseline_precision_oracle.npz, written by make_precision_golden.py from the oracle): 16
+    long-baseline curves (7000-day baselines, N = 1000) at 256 frequencies up to 20 1/d, for
+    sigma_t 0.3, 0.1 and 0.6.  QMI error |dQMI| / max(|QMI_ref|, 1e-3 max |QMI_ref|) per curve,
+    max and p99.9 over all points; largest relative error of V_J, IP_t, V_C."""
+    path = os.path.join(ROOT, "tests", "golden", "long_baseline_precision_oracle.npz")
+    if not os.path.exists(path):
+        return None
+    g = np.load(path)
+    curves = [synth.long_baseline_curve(int(k)) for k in g["k"]]
+    freqs = g["freqs"]
+    out = {"workload": "long_baseline: first %d curves, N = 1000, 7000-day baselines, %d "
+                       "frequencies each on [1e-3, 20] 1/d" % (len(curves), freqs.shape[1]),
+           "reference": "stored FP64 oracle values", "by_sigma_t": {}}
+    ctx = qmi.Context(0)
+    for st in g["widths"]:
+        tag = "%g" % st
+        rq = g["qmi_" + tag]
+        rv = (g["vj_" + tag], g["ipt_" + tag], g["vc_" + tag])
+        rec = {}
+        for name, prec in (("mixed", qmi.PREC_MIXED), ("fp64", qmi.PREC_FP64)):
+            qe, ve = [], []
+            for k, c in enumerate(curves):
+                sc, ips, _, status = ctx.periodogram([0, c.n], c.t, c.y, c.e, freqs[k], float(st),
+                                                     precision=prec, want_ips=True)
+                den = np.maximum(np.abs(rq[k]), 1e-3 * np.max(np.abs(rq[k])))
+                qe.append(np.abs(sc[0] - rq[k]) / den)
+                ve.append(max(float(np.max(np.abs(ips[0, :, i] / rv[i][k] - 1.0)))
+                              for i in range(3)))
+            q = np.concatenate(qe)
+            rec[name] = {"qmi_err_max": float(q.max()),
+                         "qmi_err_p999": float(np.quantile(q, 0.999)),
+                         "v_rel_err_max": float(max(ve)), "points": int(q.size)}
+        out["by_sigma_t"][tag] = rec
+    ctx.close()
+    return out
+
+
+def survey_report(qmi, synth, n_curves, batch=2048):
+    """Survey-scale stream (survey-stream workload: N lognormal(ln 500, 0.4) in [100, 1500], 1%
+    periodic, 30 000 coarse + 10 x 1000 refined frequencies): n_curves curves in batches with host
+    inputs (copies included), wall time; lightcurves per hour and the VALU roofline fraction on
+    wall time."""
+    wl = synth.WORKLOADS["survey_stream"]
+    kw = dict(f_min=wl["f_min"], f_max=wl["f_max"], n_coarse=wl["n_coarse"], top_k=wl["top_k"],
+              n_fine=wl["n_fine"])
+    batches = [synth.make_batch("survey_stream", range(a, min(a + batch, n_curves)))
+               for a in range(0, n_curves, batch)]
+    ctx = qmi.Context(0)
+    ctx.best_period(batches[0].offsets, batches[0].t, batches[0].y, batches[0].e,
+                    wl["sigma_t"], **kw)  # warm-up (and autotune)
+    t0 = time.perf_counter()
+    items = 0.0
+    ok = 0
+    for b in batches:
+        res, _ = ctx.best_period(b.offsets, b.t, b.y, b.e, wl["sigma_t"], **kw)
+        items += ctx.stats()["pair_items"]
+        ok += int(np.sum(res["status"] == 0))
+    dt = time.perf_counter() - t0
+    ctx.close()
+    return {"curves": n_curves, "batch": batch, "host_inputs": True, "status_ok": ok,
+            "value": n_curves / dt * 3600.0, "unit": "lightcurves/hour",
+            "gpairs_per_s": items / dt / 1e9, "roofline_frac_wall": items / dt / PEAK_ITEMS_PER_S}
+
+
+def length_sweep(qmi, synth, lengths, tile=0):
+    """Pair-kernel rate by curve length: a resident batch of equal-length curves of the survey
+    generator (enough of them for at least ~2e13 pair x frequency items, at most 4096), the
+    coarse-to-fine search of the survey batch, HIP-event time of the pair launches."""
+    import torch
+
+    wl = synth.WORKLOADS["survey_batch"]
+    kw = dict(f_min=wl["f_min"], f_max=wl["f_max"], n_coarse=wl["n_coarse"], top_k=wl["top_k"],
+              n_fine=wl["n_fine"])
+    dev = torch.device("cuda:0")
+    for n in lengths:
+        per_curve = n * (n - 1) / 2.0 * (wl["n_coarse"] + wl["top_k"] * wl["n_fine"])
+        nc = int(max(64, min(4096, math.ceil(2e13 / per_curve))))
+        b = synth.make_batch("survey_batch", range(nc), n=n)
+        T, Y, E = (torch.from_numpy(x).to(dev) for x in (b.t, b.y, b.e))
+        ctx = qmi.Context(0, stream=torch.cuda.current_stream().cuda_stream)
+        ctx.set_option(qmi.OPT_USE_GRAPH, 0)
+        if tile:
+            ctx.set_option(qmi.OPT_TILE, tile)
+        ctx.best_period_dev(b.offsets, T, Y, E, wl["sigma_t"], **kw)  # warm-up (and autotune)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.best_period_dev(b.offsets, T, Y, E, wl["sigma_t"], **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        s = ctx.stats()
+        rate = s["pair_items"] / (s["pair_kernel_ms"] * 1e-3)
+        print(json.dumps({"n": n, "curves": nc, "pair_items": s["pair_items"],
+                          "pair_kernel_ms": s["pair_kernel_ms"], "items_per_s": rate,
+                          "frac_of_peak": rate / PEAK_ITEMS_PER_S, "variant": s["pair_variant"],
+                          "wall_items_per_s": s["pair_items"] / dt,
+                          "lightcurves_per_s": nc / dt}), flush=True)
+        ctx.close()
+        del T, Y, E
+
+
 def roofline_object(achieved, probe, pair_ms, launches, traffic, variant):
     """The pair kernel against the 6-slot VALU issue bound, with the rates the probe measured in
     this run beside it: the kernel's own column body (as compiled and with the exp-interleaving
@@ -266,6 +382,11 @@ def main():
         print("bench.py runs on one GPU only: the library has no multi-GPU path (--gpus %d "
               "requested)" % a.gpus, file=sys.stderr)
         sys.exit(2)
+    if a.length_sweep:
+        from paper_1412_1840_amd import qmi, synth
+
+        length_sweep(qmi, synth, [int(x) for x in a.length_sweep.split(",")], a.tile)
+        return
     probe = None if a.no_probe else valu_probe()
     import torch
 
@@ -468,19 +589,23 @@ def main():
         classification = classification_report(
             qmi, res, [synth_curve(a.workload, k) for k in range(nc)])
 
+    precision = precision_report(qmi, synth) if a.precision else None
+    survey = survey_report(qmi, synth, a.survey_curves) if a.survey_curves > 0 else None
+
     serve = None
     sweep = None
     if a.serve_requests > 0 and a.serve_sweep:
         n_req = a.serve_requests + a.serve_warmup
         curves = [synth.serving_curve(k) for k in range(n_req)]
         sat = serving(qmi, synth, wl, st_, float("inf"), n_req, a.serve_batch, a.serve_inflight,
-                      warmup=a.serve_warmup, curves=curves)
+                      warmup=a.serve_warmup, curves=curves, max_items=a.serve_items)
         print("serving saturated: %.1f requests/s" % sat["throughput_per_s"], file=sys.stderr,
               flush=True)
         sweep = {"saturated": sat, "loads": []}
         for load in [float(x) for x in a.serve_sweep.split(",")]:
             r = serving(qmi, synth, wl, st_, load * sat["throughput_per_s"], n_req, a.serve_batch,
-                        a.serve_inflight, warmup=a.serve_warmup, curves=curves)
+                        a.serve_inflight, warmup=a.serve_warmup, curves=curves,
+                        max_items=a.serve_items)
             r["load"] = load
             print("serving at %.2f of saturation: p50 %.1f ms p99 %.1f ms, %.1f requests/s"
                   % (load, r["p50_ms"], r["p99_ms"], r["throughput_per_s"]), file=sys.stderr,
@@ -490,7 +615,7 @@ def main():
     elif a.serve_requests > 0:
         serve = serving(qmi, synth, wl, st_, a.serve_load * value,
                         a.serve_requests + a.serve_warmup, a.serve_batch, a.serve_inflight,
-                        warmup=a.serve_warmup)
+                        warmup=a.serve_warmup, max_items=a.serve_items)
 
     line = {
         "metric": METRIC,
@@ -518,6 +643,8 @@ def main():
         "metric_point": metric_point,
         "fp64_path": fp64,
         "classification": classification,
+        "precision": precision,
+        "survey_stream": survey,
         "plain": plain,
         "serving": serve,
         "serving_sweep": sweep,

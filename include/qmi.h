@@ -237,6 +237,10 @@ const char *qmi_last_error(const qmi_ctx *ctx);
 /* The autotuner chooses between variants 0 and 1, which give the same bits; variants 2 and 3
  * (forced with QMI_OPT_TILE 3 or 4) fold their row sums on 32-column chunks and round differently. */
 #define QMI_OPT_SYNC 3      /* reserved */
+/* Serving: at most this many pair x frequency items (sum over a launch's requests of
+ * N(N-1)/2 x (n_coarse + top_k n_fine)) per launch of a lane (0: no bound, the default; a single
+ * larger request still runs alone).  Read by qmi_serve_start. */
+#define QMI_OPT_SERVE_BATCH_ITEMS 4
 int qmi_set_option(qmi_ctx *ctx, int32_t option, int64_t value);
 
 /* Copy the timing of the last call into *out. */

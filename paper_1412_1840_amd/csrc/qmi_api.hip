@@ -48,6 +48,7 @@ struct qmi_ctx {
     std::string err;
     bool use_graph = true;
     int64_t tile = 0;
+    int64_t serve_batch_items = 0;  // QMI_OPT_SERVE_BATCH_ITEMS
     qmi_stats stats{};
     std::vector<hipEvent_t> ev;  // timing events (pairs: before/after each pair launch)
     int ev_used = 0;
@@ -1012,10 +1013,12 @@ struct qmi_ctx::Serve {
     size_t admit_budget = 0;
     int32_t max_batch = 256;
     int32_t max_inflight = 2;
+    double max_items = 0.0;  // pair x frequency items per launch (0: no bound)
     struct Req {
         std::vector<double> t, y, e;
         bool has_e = false;
         uint64_t tag = 0;
+        double items = 0.0;  // its pair x frequency items (coarse grid and refinement)
     };
     struct Done {
         qmi_result r;
@@ -1047,11 +1050,17 @@ void serve_worker(qmi_ctx* ctx, int lane) {
             std::unique_lock<std::mutex> lk(S->mu);
             S->cv.wait(lk, [&] { return S->stop || !S->queue.empty(); });
             if (S->stop && S->queue.empty()) return;
-            // Admit requests in arrival order while they fit this lane's share of the budget.
+            // Admit requests in arrival order while they fit this lane's share of the budget and
+            // the launch's work bound (so that a request arriving meanwhile waits for at most
+            // one bounded launch of some lane).
             const size_t share = S->admit_budget / (size_t)S->max_inflight;
+            double take_items = 0.0;
             while (!S->queue.empty() && (int32_t)take.size() < S->max_batch) {
                 size_t rb = request_bytes(S->search, (int64_t)S->queue.front().t.size());
                 if (!take.empty() && take_bytes + rb > share) break;
+                const double it = S->queue.front().items;
+                if (!take.empty() && S->max_items > 0.0 && take_items + it > S->max_items) break;
+                take_items += it;
                 take_bytes += rb;
                 take.push_back(std::move(S->queue.front()));
                 S->queue.pop_front();
@@ -1169,8 +1178,14 @@ int qmi_set_option(qmi_ctx* ctx, int32_t option, int64_t value) {
         case QMI_OPT_USE_GRAPH: ctx->use_graph = value != 0; return QMI_OK;
         case QMI_OPT_TILE: ctx->tile = value; return QMI_OK;
         case QMI_OPT_SYNC: return QMI_OK;
-        default: set_err(ctx, "unknown option %d", option); return QMI_EINVAL;
+        case QMI_OPT_SERVE_BATCH_ITEMS:
+            if (value < 0) break;
+            ctx->serve_batch_items = value;
+            return QMI_OK;
+        default: break;
     }
+    set_err(ctx, "unknown option %d or bad value %lld", option, (long long)value);
+    return QMI_EINVAL;
 }
 
 int qmi_get_stats(const qmi_ctx* ctx, qmi_stats* out) {
@@ -1636,6 +1651,7 @@ int qmi_serve_start(qmi_ctx* ctx, const qmi_kernel_params* kp, const qmi_search*
     S->admit_budget = admit_budget_bytes ? admit_budget_bytes : ctx->budget / 2;
     S->max_batch = max_batch;
     S->max_inflight = max_inflight;
+    S->max_items = ctx->serve_batch_items > 0 ? (double)ctx->serve_batch_items : 0.0;
     const size_t lane_budget = ctx->budget / (size_t)max_inflight;
     for (int i = 0; i < max_inflight; ++i) {
         qmi_ctx* lc = nullptr;
@@ -1678,6 +1694,8 @@ int qmi_submit(qmi_ctx* ctx, const double* t, const double* y, const double* e, 
             r.has_e = true;
         }
         r.tag = tag;
+        r.items = 0.5 * (double)n * (double)(n - 1) *
+                  ((double)S->search.n_coarse + (double)S->search.top_k * S->search.n_fine);
         S->queue.push_back(std::move(r));
         S->queued_bytes += rb;
     }

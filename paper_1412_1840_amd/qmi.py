@@ -36,6 +36,7 @@ PREC_FP64 = 1
 PREC_FOLD32 = 2  # precision control only: phase fold in FP32
 OPT_USE_GRAPH = 1
 OPT_TILE = 2
+OPT_SERVE_BATCH_ITEMS = 4
 NOT_PERIODIC, PERIODIC, UNDECIDED = 0, 1, 255
 MAX_N = 8192
 MAX_TOPK = 32
@@ -432,7 +433,9 @@ class Context:
                     n_coarse: int = 20000,
                     top_k: int = 10, n_fine: int = 1000, sigma_y: float = SIGMA_SILVERMAN,
                     score: int = SCORE_QMI, admit_budget_bytes: int = 0, max_batch: int = 256,
-                    max_inflight: int = 2):
+                    max_inflight: int = 2, max_batch_items: float = 0):
+        """max_batch_items > 0 bounds each launch's pair x frequency items."""
+        self.set_option(OPT_SERVE_BATCH_ITEMS, int(max_batch_items))
         kp = kernel_params(sigma_t, sigma_y, PREC_MIXED)
         s = search(f_min, f_max, n_coarse, top_k, n_fine, score)
         self._check(lib().qmi_serve_start(self._h, ctypes.byref(kp), ctypes.byref(s),

@@ -76,7 +76,22 @@ def test_trials_and_best_match_oracle(ctx, n_grid):
         assert res[k]["status"] == 0
         assert res[k]["n_peaks"] == int(np.sum(~np.isnan(rf)))
         if not np.array_equal(trials[k], rf, equal_nan=True):
-            continue  # scores are compared where the lists agree
+            # A near-tie of the window values changed the list (checked above): score the GPU's
+            # own list with the oracle, and check the GPU's scores and its best trial on it.
+            okg = ~np.isnan(trials[k])
+            gq = O.qmi(O.information_potentials(c.t, c.y, 0.3, O.silverman_sigma(c.y),
+                                                trials[k][okg]))
+            den = np.maximum(np.abs(gq), 1e-3 * np.max(np.abs(gq)))
+            assert np.max(np.abs(scores[k][okg] - gq) / den) <= QMI_TOL, (k, c.n)
+            pos = np.flatnonzero(okg)
+            want = min(range(len(gq)), key=lambda i: (-gq[i], trials[k][pos[i]], i))
+            got = int(res[k]["coarse_index"])
+            if got != pos[want]:
+                i = int(np.flatnonzero(pos == got)[0])
+                assert gq[want] - gq[i] <= QMI_TOL * abs(gq[want]), (k, c.n)
+            else:
+                assert res[k]["f_best"] == trials[k][got]
+            continue
         rq = np.full(n_keep * n_trials, np.nan)
         ok = ~np.isnan(rf)
         rq[ok] = ref["scores"]
