@@ -417,16 +417,20 @@ def main():
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()
+    print("bench: %d warm-up steps done" % a.warmup, file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     pair_ms = 0.0
     items = 0.0
     launches = 0
-    for _ in range(a.steps):
+    for i in range(a.steps):
         res = step()
         s = ctx.stats()
         pair_ms += s["pair_kernel_ms"]
         items += s["pair_items"]
         launches += s["pair_launches"]
+        if (i + 1) % 5 == 0:
+            print("bench: %d of %d timed steps done" % (i + 1, a.steps), file=sys.stderr,
+                  flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ok = int(np.sum(res["status"] == 0))
@@ -590,7 +594,9 @@ def main():
             qmi, res, [synth_curve(a.workload, k) for k in range(nc)])
 
     precision = precision_report(qmi, synth) if a.precision else None
+    print("bench: precision leg done", file=sys.stderr, flush=True)
     survey = survey_report(qmi, synth, a.survey_curves) if a.survey_curves > 0 else None
+    print("bench: survey-stream leg done", file=sys.stderr, flush=True)
 
     serve = None
     sweep = None
