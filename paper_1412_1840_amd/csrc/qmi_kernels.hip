@@ -387,6 +387,19 @@ __device__ __forceinline__ int fresh_lane() {
     return l;
 }
 
+// Exponent offset of a row in the diagonal region: 0, or +inf for a masked row (g = 0).  The
+// choice is wave-uniform and made on the scalar unit (an integer select of the bit pattern), so
+// that the offset is a scalar operand of the kernel-argument FMA and costs no VALU instruction.
+template <typename R>
+__device__ __forceinline__ R mask_offset(bool masked) {
+    if constexpr (sizeof(R) == 4) {
+        return __int_as_float(__builtin_amdgcn_readfirstlane(masked ? 0x7f800000 : 0));
+    } else {
+        const int hi = __builtin_amdgcn_readfirstlane(masked ? 0x7ff00000 : 0);
+        return __longlong_as_double((long long)hi << 32);
+    }
+}
+
 // Adds v to a lane-private LDS accumulator without returning the old value (ds_add_f64).
 __device__ __forceinline__ void ladd(double* p, double v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
@@ -481,7 +494,7 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
     using V = typename W::V;
     constexpr int ROWS = rows_per_wave<R>();
     constexpr int PASS = kWaves * ROWS;
-    constexpr int GRP = 2;  // rows skipped together in the diagonal region
+    constexpr int GRP = 4;  // rows skipped together in the diagonal region
     __shared__ V ph[2][CH][kLanes];
     __shared__ double fq[kLanes];  // the lane's frequency, re-read where the warp is formed
     __shared__ double acc[3][kWaves][kLanes];  // this piece's SJ, ST, SC per wave (added to in place)
@@ -553,7 +566,6 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
     const double* rr = rd_all + P.off;
     const double scale = uniform(sqrt(sqrt(2.0 * kLog2e) / P.sigma_t));
     const R zero = R(0);
-    const R pinf = uniform((R)INFINITY);
 
     // The FP64 sums SJ, ST and SC = SCa + SCb of this lane live in LDS and are added to in place,
     // so that no registers are held for them across the column loops.
@@ -673,7 +685,7 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
                         if (g0 < cnt) {
 #pragma unroll
                             for (int m = g0; m < g0 + GRP; ++m) {
-                                const R off = (m < cnt) ? zero : pinf;
+                                const R off = mask_offset<R>(m >= cnt);
                                 if (m < kPartials)
                                     pair_term<R, true>(ci[m], si[m], u.x, u.y, off, kk[m], Tp[m],
                                                        G[m], Jp[m]);
