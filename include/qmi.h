@@ -234,8 +234,8 @@ const char *qmi_last_error(const qmi_ctx *ctx);
 /* Options (qmi_set_option). */
 #define QMI_OPT_USE_GRAPH 1 /* 1: capture the device section into a hipGraph and replay it (default 1) */
 #define QMI_OPT_TILE 2      /* pair-kernel variant: 0 autotuned per length bucket, k > 0 variant k-1 */
-/* The autotuner chooses between variants 0 and 1, which give the same bits; variants 2 and 3
- * (forced with QMI_OPT_TILE 3 or 4) fold their row sums on 32-column chunks and round differently. */
+/* Variants 0-3: 2 or 4 waves per SIMD with 64- or 32-column chunks.  They give the same bits; the
+ * autotuner times them on the first large call of each length bucket and keeps the fastest. */
 #define QMI_OPT_SYNC 3      /* reserved */
 /* Serving: at most this many pair x frequency items (sum over a launch's requests of
  * N(N-1)/2 x (n_coarse + top_k n_fine)) per launch of a lane (0: no bound, the default; a single

@@ -862,10 +862,10 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
         }
     }
     if (tune_now) {
-        // Time the 64-column variants (0 and 1, which differ only in occupancy and give the same
-        // bits, so that tuning never changes a result) on the largest curves of this group (the
+        // Time the four variants (2 or 4 waves per SIMD, 64- or 32-column chunks; they give the
+        // same bits, so tuning never changes a result) on the largest curves of this group (the
         // first in LPT order) over a slice of the same frequency plan, into a scratch output, and
-        // keep the fastest.  The 32-column variants are reached only through QMI_OPT_TILE.
+        // keep the fastest for this length bucket.
         const int pc = std::min(nc, 48);
         FreqPlan probe = fp;
         probe.count = (int32_t)std::min<int64_t>(F1, 64 * 24);
@@ -879,7 +879,7 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
         HIP_OK(ctx, hipEventCreate(&e1));
         float best_ms = 0.f;
         int best_v = 0;
-        for (int v = 0; v < std::min(nvar, 2); ++v) {
+        for (int v = 0; v < nvar; ++v) {
             HIP_OK(ctx,
                    launch_pairs<R>(st, dcp, dorder, pc, probe, t, K, rd, rp, ks, pout, v, 0));
             HIP_OK(ctx, hipEventRecord(e0, st));

@@ -480,9 +480,10 @@ __device__ __forceinline__ void pair_scores(const CurveParams& P, double SJ, dou
 // single piece and stores its sums in out.part, for pair_epilogue_kernel to add in the same order
 // (SPLIT true): both give the same bits.
 // Variants: WPE is the occupancy target in waves per SIMD (2: the registers of 2 waves; 4: at most
-// 128 VGPRs, so two workgroups share a CU), CH the columns per LDS chunk; the host autotuner
-// chooses WPE with CH = 64 (the same bits either way), CH = 32 is used only on request.  PULLK
-// (per-curve frequency lists) reads each column's K block while staging it.
+// 128 VGPRs, so two workgroups share a CU), CH the columns per LDS chunk; all four give the same
+// bits (the row sums are folded every 64 columns whatever the chunk), and the host autotuner
+// chooses among them per length bucket.  PULLK (per-curve frequency lists) reads each column's K
+// block while staging it.
 template <typename R, int WPE, int CH, bool FOLD32 = false, bool PULLK = false, bool SPLIT = false>
 __global__ void __launch_bounds__(kThreads, WPE)
 pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ order,
@@ -625,6 +626,7 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
         // Chunks in segment order: the inner loop runs the chunks of one column segment, the
         // segment's piece is folded into the totals after it.
         constexpr int kSegChunks = PASS / CH;
+        constexpr int kRowFold = 64;  // columns per FP32 run of the row sums
         for (int k = 0; k < nch;) {
           const int kend = min(nch, (k / kSegChunks + 1) * kSegChunks);
           for (; k < kend; ++k) {
@@ -709,17 +711,22 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
                     ladd(aSC, Td * rr[j]);
                 }
             }
-            // Row sums of this chunk, weighted by the FP64 row sums r_i.
-            double rk[ROWS];
+            // Row sums of the last kRowFold columns (or of the segment's or pass's last,
+            // shorter run), weighted by the FP64 row sums r_i.  The fold points do not depend on
+            // CH, so that the variants' results are the same bits.
+            static_assert(kRowFold % CH == 0, "chunks tile the row-sum runs");
+            if ((k + 1) % (kRowFold / CH) == 0 || k + 1 == kend) {
+                double rk[ROWS];
 #pragma unroll
-            for (int m = 0; m < ROWS; ++m) rk[m] = rpb[m];
-            double sca = 0.0;
+                for (int m = 0; m < ROWS; ++m) rk[m] = rpb[m];
+                double sca = 0.0;
 #pragma unroll
-            for (int m = 0; m < ROWS; ++m) {
-                sca = fma((double)G[m], rk[m], sca);
-                G[m] = R(0);
+                for (int m = 0; m < ROWS; ++m) {
+                    sca = fma((double)G[m], rk[m], sca);
+                    G[m] = R(0);
+                }
+                ladd(aSC, sca);
             }
-            ladd(aSC, sca);
             __syncthreads();
           }
           // The segment's piece is complete: its sums, the waves' sums in wave order, are added

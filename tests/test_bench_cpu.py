@@ -35,5 +35,6 @@ def test_digest_ignores_comments_and_white_space_only(tmp_path):
     text = k.read_text()
     k.write_text("// an added comment\n/* and a block\n   comment */\n" + text.replace("\n", "\n\n"))
     assert bench.kernel_code_digest(str(tmp_path)) == base
-    k.write_text(text.replace("constexpr int GRP = 2;", "constexpr int GRP = 4;"))
+    assert "constexpr int kRowFold = 64;" in text
+    k.write_text(text.replace("constexpr int kRowFold = 64;", "constexpr int kRowFold = 128;"))
     assert bench.kernel_code_digest(str(tmp_path)) != base

@@ -425,9 +425,10 @@ def test_one_piece_per_workgroup_launches_give_the_same_bits(ctx):
 
 
 def test_pair_kernel_variants_agree(ctx):
-    """Every pair-kernel variant the autotuner can pick meets the oracle bar; variants that differ
-    only in occupancy give identical bits."""
-    curves = [synth.survey_batch_curve(k, n=n) for k, n in enumerate([70, 300, 777])]
+    """Every pair-kernel variant the autotuner can pick meets the oracle bar, and all four (2 or 4
+    waves per SIMD, 64- or 32-column chunks) give identical bits, on lengths that end their passes
+    and column segments inside a 32-column chunk and on both launch forms."""
+    curves = [synth.survey_batch_curve(k, n=n) for k, n in enumerate([70, 300, 777, 529, 1100])]
     b = pack(curves)
     freqs = O.linear_grid(1e-3, 10.0, 190)
     refs = [O.qmi(oracle_ips(c, freqs)) for c in curves]
@@ -440,8 +441,19 @@ def test_pair_kernel_variants_agree(ctx):
             out[v] = sc
             for k in range(len(curves)):
                 assert floor_rel(sc[k], refs[k]).max() <= QMI_TOL, (v, k)
-    assert np.array_equal(out[1], out[2])  # chunk 64, occupancy 2 vs 4
-    assert np.array_equal(out[3], out[4])  # chunk 32
+    for v in (2, 3, 4):
+        assert np.array_equal(out[1], out[v]), v
+    # the batched launch form (whole tiles per workgroup) gives the same bits in every variant
+    many = [synth.survey_batch_curve(50 + k, n=300 + 37 * k) for k in range(40)]
+    bm = pack(many)
+    fm = O.linear_grid(1e-3, 10.0, 3300)
+    outs = []
+    with qmi.Context(0) as c3:
+        for v in range(1, 5):
+            c3.set_option(qmi.OPT_TILE, v)
+            outs.append(c3.periodogram(bm.offsets, bm.t, bm.y, bm.e, fm, 0.3)[0])
+    for v in (1, 2, 3):
+        assert np.array_equal(outs[0], outs[v]), v
 
 
 def test_autotune_on_batch_larger_than_probe(ctx):
