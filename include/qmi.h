@@ -122,7 +122,10 @@ typedef struct {
 } qmi_kernel_params;
 
 /*
- * Coarse-to-fine search.  The coarse grid is f_k = f_min + k * ((f_max - f_min) / (n_coarse - 1)),
+ * Coarse-to-fine search for the frequency that maximises the score (Sec. 3; the refined peaks are
+ * the highest local maxima of the coarse periodogram, the selection the bands method of Sec. 3.1
+ * applies to its spectral windows).  The coarse grid is
+ * f_k = f_min + k * ((f_max - f_min) / (n_coarse - 1)),
  * k = 0 .. n_coarse-1.  Its local maxima (q_k > q_{k-1} and q_k >= q_{k+1}; q_0 >= q_1 at the first
  * point, q_{F-1} > q_{F-2} at the last) are ranked by score, ties to the lower k, and the best top_k
  * are each refined on n_fine evenly spaced points of [f_{k-1}, f_{k+1}] ([f_0, f_1], [f_{F-2},
@@ -276,9 +279,15 @@ int qmi_periodogram(qmi_ctx *ctx, const qmi_batch *batch, const qmi_kernel_param
                     double *ips_out, double *ip_y_out, int32_t *status_out);
 
 /*
- * Best period of each curve by the coarse-to-fine search of qmi_search.
- *   out         host, [n_curves]
+ * Best period of each curve by the coarse-to-fine search of qmi_search.  The period estimate is the
+ * trial frequency that maximises the score for fixed kernel widths (Sec. 3, where the CKP is
+ * maximised over trial frequencies); the trial frequencies are refinement windows around the
+ * highest local maxima of a coarse periodogram, as the bands method of Sec. 3.1 takes the highest
+ * local maxima of its spectral windows.
+ *   out         host, [n_curves]; coarse_index, peak_rank, fine_index locate f_best in the search
  *   coarse_out  nullable host, [n_curves * n_coarse]: the coarse periodogram of the searched score
+ * Per-curve problems set out[k].status (QMI_EINVAL for N < 2 or a non-finite sample,
+ * QMI_EDEGENERATE for a zero width) with NaN scores; call-level errors leave out untouched.
  */
 int qmi_best_period(qmi_ctx *ctx, const qmi_batch *batch, const qmi_kernel_params *kp,
                     const qmi_search *search, qmi_result *out, double *coarse_out);
