@@ -377,23 +377,27 @@ def test_serving_results_equal_alone(ctx):
     mixed, _ = ctx.best_period(batch.offsets, batch.t, batch.y, batch.e, 0.3, **kw)
     for k in range(6):
         assert np.array_equal(mixed[k], alone[k])
-    with qmi.Context(0) as srv:
-        srv.serve_start(0.3, max_batch=8, max_inflight=3, **kw)
-        got = {}
-        for k, c in enumerate(curves):
-            while not srv.submit(c.t, c.y, c.e, tag=k):
-                res, tags = srv.poll(64, 1000)
+    # unbounded launches of up to 8 requests on 3 lanes, then launches bounded to about two
+    # requests' pair work on 4 lanes
+    for max_batch, inflight, items in ((8, 3, 0), (64, 4, 2.5e8)):
+        with qmi.Context(0) as srv:
+            srv.serve_start(0.3, max_batch=max_batch, max_inflight=inflight,
+                            max_batch_items=items, **kw)
+            got = {}
+            for k, c in enumerate(curves):
+                while not srv.submit(c.t, c.y, c.e, tag=k):
+                    res, tags = srv.poll(64, 1000)
+                    got.update({int(t): r for t, r in zip(tags, res)})
+                if k % 7 == 0:
+                    time.sleep(0.002)
+            t0 = time.time()
+            while len(got) < len(curves) and time.time() - t0 < 60:
+                res, tags = srv.poll(64, 10000)
                 got.update({int(t): r for t, r in zip(tags, res)})
-            if k % 7 == 0:
-                time.sleep(0.002)
-        t0 = time.time()
-        while len(got) < len(curves) and time.time() - t0 < 60:
-            res, tags = srv.poll(64, 10000)
-            got.update({int(t): r for t, r in zip(tags, res)})
-        srv.serve_stop()
-    assert len(got) == len(curves)
-    for k in range(len(curves)):
-        assert np.array_equal(got[k], mixed[k]), k
+            srv.serve_stop()
+        assert len(got) == len(curves)
+        for k in range(len(curves)):
+            assert np.array_equal(got[k], mixed[k]), (items, k)
 
 
 def test_one_piece_per_workgroup_launches_give_the_same_bits(ctx):

@@ -71,3 +71,19 @@ def test_search_reports_the_rule_width_and_matches_the_oracle():
         assert (res["coarse_index"][k], res["fine_index"][k]) == (ref.coarse_index,
                                                                   ref.fine_index), k
         assert res["score_nckp"][k] == pytest.approx(ref.nckp, rel=1e-4)
+
+
+def test_bands_front_end_with_the_rule():
+    """The bands method's trial scores use each curve's own sigma_t from the rule."""
+    curves = _curves()[:6]
+    b = synth.pack(curves)
+    with qmi.Context(0) as ctx:
+        res, trials, scores = ctx.bands_best_period(b.offsets, b.t, b.y, b.e,
+                                                    qmi.SIGMA_T_SKEWNESS, n_trials=40)
+    for k, c in enumerate(curves):
+        st = O.sigma_t_skewness(c.y)
+        assert res["sigma_t"][k] == pytest.approx(st, rel=1e-14)
+        ok = ~np.isnan(trials[k])
+        ref = O.qmi(O.information_potentials(c.t, c.y, st, O.silverman_sigma(c.y),
+                                             trials[k][ok]))
+        assert floor_rel(scores[k][ok], ref).max() <= QMI_TOL, k
