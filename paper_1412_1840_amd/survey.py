@@ -4,7 +4,7 @@ stopped and produces the same bytes as an uninterrupted one.
 
 Layout of an output directory:
 
-* ``results.bin``      one ``qmi.RESULT_DTYPE`` record (96 bytes) per curve, in curve order;
+* ``results.bin``      one ``qmi.RESULT_DTYPE`` record (104 bytes) per curve, in curve order;
 * ``checkpoint.json``  the run's configuration, the number of curves whose records are in
                        ``results.bin``, that file's length at that point, and running totals
                        (pair items, pair-kernel and wall time).
