@@ -585,11 +585,20 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
     for (int base = SPLIT ? p_lo * PASS : 0; base < base_end; base += PASS) {
         // This wave's rows: base + w + kWaves * m, m < nrows.
         const int nrows = uniform(min(ROWS, max(0, (n - base - w + kWaves - 1) / kWaves)));
+        // Columns [cbeg, cend): the whole pass, or the piece's segment.
+        const int cbeg = SPLIT ? s_only * PASS : base;
+        const int cend = SPLIT ? min(n, cbeg + PASS) : n;
+        const int nch = (cend - cbeg + CH - 1) / CH;
+        // Where the columns start at the pass's own rows (every launch but the off-diagonal
+        // pieces of a split one), the rows' warp vectors are the staged vectors of the diagonal
+        // block's columns, read from LDS as each chunk arrives (rows_from_chunk below); they
+        // start at zero, as do rows past the end of the curve.  Otherwise they are formed here.
+        const bool rows_staged = (cbeg == base);
         R ci[ROWS], si[ROWS], G[ROWS];
 #pragma unroll
         for (int m = 0; m < ROWS; ++m) {
             const int i = base + w + kWaves * m;
-            V u = (m < nrows) ? W::at(fq[lane], t[i], scale) : V{R(0), R(0)};
+            V u = (!rows_staged && m < nrows) ? W::at(fq[lane], t[i], scale) : V{R(0), R(0)};
             ci[m] = u.x;
             si[m] = u.y;
             G[m] = R(0);
@@ -598,10 +607,6 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
         const R* Kbase = K_all + P.koff + kofs;
         const double* rpb = rp_all + P.poff + kofs;
         const R* ksb = ks_all + P.ksoff + (int64_t)((base / PASS) * kWaves + w) * n;
-        // Columns [cbeg, cend): the whole pass, or the piece's segment.
-        const int cbeg = SPLIT ? s_only * PASS : base;
-        const int cend = SPLIT ? min(n, cbeg + PASS) : n;
-        const int nch = (cend - cbeg + CH - 1) / CH;
 
         // With per-curve frequency lists (a few tiles per curve, as in the bands method) the
         // workgroups of a curve run side by side and every column's scalar K loads would miss the
@@ -626,6 +631,27 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
         // Chunks in segment order: the inner loop runs the chunks of one column segment, the
         // segment's piece is folded into the totals after it.
         constexpr int kSegChunks = PASS / CH;
+        // Chunk k of the diagonal block holds the columns base + k CH ... + CH - 1, among them
+        // this wave's rows m in [k RPC, (k + 1) RPC), at the chunk's columns w + kWaves r,
+        // r = m - k RPC: they are read from it before its columns are used.  A column j pairs
+        // only with rows i < j, so that every row a column of chunk k pairs with has been read
+        // by then (and the masked groups of GRP rows stay inside the rows read, RPC being a
+        // multiple of GRP).  k is wave-uniform; a row takes the value read for it by a select on
+        // k, so that every register index stays static.
+        constexpr int RPC = CH / kWaves;
+        static_assert(CH % kWaves == 0 && PASS % CH == 0, "chunks tile the diagonal block");
+        static_assert(RPC % GRP == 0, "masked groups stay inside the rows read");
+        auto rows_from_chunk = [&](int k, int buf) {
+            V u[RPC];
+#pragma unroll
+            for (int r = 0; r < RPC; ++r) u[r] = ph[buf][w + kWaves * r][lane];
+#pragma unroll
+            for (int m = 0; m < ROWS; ++m) {
+                const bool mine = (m / RPC == k);
+                ci[m] = mine ? u[m % RPC].x : ci[m];
+                si[m] = mine ? u[m % RPC].y : si[m];
+            }
+        };
         constexpr int kRowFold = 64;  // columns per FP32 run of the row sums
         for (int k = 0; k < nch;) {
           const int kend = min(nch, (k / kSegChunks + 1) * kSegChunks);
@@ -633,6 +659,7 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
             const int j0 = cbeg + k * CH;
             if (k + 1 < nch) stage(j0 + CH, (k + 1) & 1);
             const int buf = k & 1;
+            if (rows_staged && k < kSegChunks) rows_from_chunk(k, buf);
             const int jend = min(CH, n - j0);
             // Columns of this chunk.  Past the diagonal block of the pass every row of a full wave
             // pairs with every column (straight-line body); in the diagonal block, or for a wave
