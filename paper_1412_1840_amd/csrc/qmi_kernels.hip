@@ -703,6 +703,11 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
                     R kk[ROWS];
 #pragma unroll
                     for (int m = 0; m < ROWS; ++m) kk[m] = kr[m];
+                    // The column's kernel values are loaded together here, before the groups'
+                    // branches, so that the column waits once for its scalar loads rather than
+                    // once in each group that needs more of them.
+#pragma unroll
+                    for (int m = 0; m < ROWS; ++m) asm volatile("" : "+s"(kk[m]));
                     R Tp[kPartials], Jp[kPartials];
                     // Masked rows get an exponent offset of +inf (g = 0, adding exactly nothing);
                     // groups of GRP rows that are entirely masked are skipped.  cnt and the
