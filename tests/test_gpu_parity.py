@@ -609,10 +609,24 @@ def test_benchmark_launch_configuration_sampled():
         assert floor_rel(got, ref).max() <= QMI_TOL, k
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
                         "survey_batch_oracle.json")
-    for g in json.load(open(path))["curves"]:
+    gold = json.load(open(path))
+    exact, ties = 0, []
+    for g in gold["curves"]:
         r = res[g["k"]]
-        assert (r["coarse_index"], r["fine_index"]) == (g["coarse_index"], g["fine_index"]), g["k"]
-        assert r["f_best"] == g["f_best"]
+        if (r["coarse_index"], r["fine_index"]) == (g["coarse_index"], g["fine_index"]):
+            assert r["f_best"] == g["f_best"]
+            exact += 1
+            continue
+        # A flat maximum (the oracle's best and runner-up refined scores within 1e-5 of each
+        # other) has several correct grid points: the GPU's choice must then score within that
+        # margin of the best under the oracle, as in the other full-search comparisons.
+        cv = b.curve(g["k"])
+        q = O.qmi(O.information_potentials(cv.t, cv.y, gold["sigma_t"], g["sigma_y"],
+                                           [r["f_best"]]))[0]
+        assert g["best_gap"] <= 1e-5 * abs(g["score"]) and q >= g["score"] * (1 - 1e-5), g["k"]
+        ties.append((g["k"], g["fine_index"], int(r["fine_index"])))
+    print("benchmark launch: %d of %d stored searches identical, %d flat-maximum ties %s"
+          % (exact, len(gold["curves"]), len(ties), ties))
 
 
 def test_small_hbm_budget_splits_the_batch_into_groups():
