@@ -456,9 +456,11 @@ def main():
     plain = None
     if a.plain_sample > 0:
         ks = list(range(min(a.plain_sample, nc)))
-        # One untimed single-curve call first: the first call of this launch form sizes the
-        # context's buffer of piece sums (one allocation), which is not part of the path.
-        lo, hi = int(batch.offsets[ks[-1]]), int(batch.offsets[ks[-1] + 1])
+        # One untimed single-curve call first, on the sample's longest curve: it sizes the
+        # context's buffers for this launch form (the piece sums, the K table), as a long run of
+        # per-curve calls would have them; allocation is not part of the path.
+        kmax = max(ks, key=lambda k: int(batch.offsets[k + 1] - batch.offsets[k]))
+        lo, hi = int(batch.offsets[kmax]), int(batch.offsets[kmax + 1])
         ctx.best_period_dev([0, hi - lo], T[lo:hi], Y[lo:hi], E[lo:hi], st_, **kw)
         torch.cuda.synchronize()
         p0 = time.perf_counter()

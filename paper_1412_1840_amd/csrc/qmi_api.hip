@@ -157,7 +157,10 @@ int ensure(qmi_ctx* ctx, int id, size_t bytes) {
     if (bytes == 0) bytes = 256;
     ctx->in_use |= 1ull << id;
     if (b.bytes >= bytes) return QMI_OK;
-    size_t want = bytes + bytes / 8;  // some headroom for the next call
+    // Some headroom for the next call, and at least twice the old size when a buffer grows, so
+    // that a run of calls on curves of increasing length reallocates (and synchronises the
+    // device in hipFree) only a logarithmic number of times.
+    size_t want = std::max(bytes + bytes / 8, 2 * b.bytes);
     if (ctx->allocated - b.bytes + want > ctx->budget) {
         // Release buffers the current operation does not use before giving up.
         for (int k = 0; k < qmi_ctx::kNumBufs; ++k)
