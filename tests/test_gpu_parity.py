@@ -1,6 +1,6 @@
 """Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
 
-Tolerances (derived in the design doc from the arithmetic): the mixed-precision path evaluates each
+Tolerances, derived from the arithmetic: the mixed-precision path evaluates each
 kernel value in FP32 (argument error ~ a few ulp of log2(e)/sigma_t^2, exp2 ~1 ulp) and sums short
 runs in FP32 before folding into FP64, so the three information potentials carry relative errors of
 order 1e-7; the score target is the per-frequency QMI relative error <= 1e-4, measured against
