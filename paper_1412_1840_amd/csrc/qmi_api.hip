@@ -667,7 +667,7 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
         HIP_OK(ctx, launch_prologue(st, dcp, nc, max_n, t, y, e, skew_lambda, skew_mu));
         HIP_OK(ctx, launch_gram<R>(st, dcp, nc, rows, drow, y, K, rp, rd));
         HIP_OK(ctx, launch_gram_finalize<R>(st, dcp, nc, rd, rp));
-        HIP_OK(ctx, launch_ksum<R>(st, dcp, nc, K, ks));
+        HIP_OK(ctx, launch_ksum<R>(st, dcp, nc, max_n, K, ks));
         if (bp) HIP_OK(ctx, launch_bands(st, dcp, nc, max_n, t, y, bd));
         if (events) pair_event_idx.push_back(ctx->ev_used);
         rec();

@@ -187,7 +187,8 @@ template <typename R>
 hipError_t launch_gram_finalize(hipStream_t st, CurveParams* cp, int n_curves, const double* rd,
                                 double* rp);
 template <typename R>
-hipError_t launch_ksum(hipStream_t st, const CurveParams* cp, int n_curves, const R* K, R* ks);
+hipError_t launch_ksum(hipStream_t st, const CurveParams* cp, int n_curves, int max_n, const R* K,
+                       R* ks);
 // Pair-kernel variants: ids 0 .. pair_variants<R>() - 1 (0 is the default), and for R = float
 // kVariantFold32, the shape of variant 0 with the phase fold in FP32 (a precision control).
 // split_pmax > 0 (with out.part): one (pass, column segment) piece per workgroup, at most

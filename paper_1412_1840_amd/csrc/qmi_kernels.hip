@@ -253,7 +253,9 @@ gram_finalize_kernel(CurveParams* __restrict__ cp, const double* __restrict__ rd
 // kernel accumulates K(i, j) g_ij: kPartials interleaved partials (rows m mod kPartials, each row
 // by row with an fma), combined as the kernel combines them.  Where every g_ij of a column is
 // exactly 1 (coincident phases, f = 0) the kernel's column sum equals this value bit for bit, so
-// their difference is exactly zero.  One block per curve.
+// their difference is exactly zero.  blockIdx.x is the curve; the curve's (pass, wave, column)
+// entries are dealt over the gridDim.y blocks of its row (each entry is computed alone, so the
+// split does not change a value).
 constexpr int kKsBlock = 256;
 
 template <typename R>
@@ -267,7 +269,8 @@ ksum_kernel(const CurveParams* __restrict__ cp, const R* __restrict__ K, R* __re
     const int n = P.n;
     const int passes = (n + PASS - 1) / PASS;
     const int64_t total = (int64_t)passes * kWaves * n;
-    for (int64_t e = threadIdx.x; e < total; e += kKsBlock) {
+    for (int64_t e = (int64_t)blockIdx.y * kKsBlock + threadIdx.x; e < total;
+         e += (int64_t)gridDim.y * kKsBlock) {
         const int j = (int)(e % n);
         const int pw = (int)(e / n);
         const int w = pw % kWaves, base = (pw / kWaves) * PASS;
@@ -874,13 +877,21 @@ template hipError_t launch_gram_finalize<double>(hipStream_t, CurveParams*, int,
                                                  double*);
 
 template <typename R>
-hipError_t launch_ksum(hipStream_t st, const CurveParams* cp, int n_curves, const R* K, R* ks) {
+hipError_t launch_ksum(hipStream_t st, const CurveParams* cp, int n_curves, int max_n, const R* K,
+                       R* ks) {
     if (n_curves <= 0) return hipSuccess;
-    ksum_kernel<R><<<n_curves, kKsBlock, 0, st>>>(cp, K, ks);
+    // Enough blocks per curve for its longest member's entries to take a few steps per thread,
+    // and no more than the chip needs when there are many curves.
+    constexpr int PASS = kWaves * rows_per_wave<R>();
+    const int64_t entries = (int64_t)((max_n + PASS - 1) / PASS) * kWaves * max_n;
+    int per_curve = (int)std::min<int64_t>(64, (entries + 4 * kKsBlock - 1) / (4 * kKsBlock));
+    per_curve = std::max(1, std::min(per_curve, (2048 + n_curves - 1) / n_curves));
+    ksum_kernel<R><<<dim3(n_curves, per_curve), kKsBlock, 0, st>>>(cp, K, ks);
     return hipGetLastError();
 }
-template hipError_t launch_ksum<float>(hipStream_t, const CurveParams*, int, const float*, float*);
-template hipError_t launch_ksum<double>(hipStream_t, const CurveParams*, int, const double*,
+template hipError_t launch_ksum<float>(hipStream_t, const CurveParams*, int, int, const float*,
+                                       float*);
+template hipError_t launch_ksum<double>(hipStream_t, const CurveParams*, int, int, const double*,
                                         double*);
 
 template <typename R>
