@@ -695,6 +695,47 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
                     ladd(aSJ, (double)(Jq - ksj));
                     ladd(aSC, Td * rj);
                 }
+            } else if (nrows == ROWS && j0 >= base + PASS / 2) {
+                // The upper half of the diagonal block: every column pairs with all of the
+                // wave's rows below base + PASS / 2 (the first half, a straight-line body) and
+                // with the first cnt - ROWS / 2 of the others (masked in groups as below).
+                constexpr int HALF = ROWS / 2;
+                for (int q = 0; q < jend; ++q) {
+                    const int j = j0 + q;
+                    const int cnt = uniform(min(ROWS, (j - base - w + kWaves - 1) / kWaves));
+                    const V u = ph[buf][q][lane];
+                    const R* kr = Kbase + (int64_t)j * P.npad;
+                    R kk[ROWS];
+#pragma unroll
+                    for (int m = 0; m < ROWS; ++m) kk[m] = kr[m];
+#pragma unroll
+                    for (int m = 0; m < ROWS; ++m) asm volatile("" : "+s"(kk[m]));
+                    R Tp[kPartials], Jp[kPartials];
+#pragma unroll
+                    for (int m = 0; m < kPartials; ++m)
+                        pair_term<R, true>(ci[m], si[m], u.x, u.y, zero, kk[m], Tp[m], G[m],
+                                           Jp[m]);
+#pragma unroll
+                    for (int m = kPartials; m < HALF; ++m)
+                        pair_term<R>(ci[m], si[m], u.x, u.y, zero, kk[m], Tp[m % kPartials],
+                                     G[m], Jp[m % kPartials]);
+                    interleave_exps<R, HALF>();
+#pragma unroll
+                    for (int g0 = HALF; g0 < ROWS; g0 += GRP) {
+                        if (g0 < cnt) {
+#pragma unroll
+                            for (int m = g0; m < g0 + GRP; ++m)
+                                pair_term<R>(ci[m], si[m], u.x, u.y, mask_offset<R>(m >= cnt),
+                                             kk[m], Tp[m % kPartials], G[m], Jp[m % kPartials]);
+                        }
+                    }
+                    const R Tq = combine_partials(Tp);
+                    const R Jq = combine_partials(Jp);
+                    const double Td = (double)Tq;
+                    ladd(aST, Td);
+                    ladd(aSJ, (double)(Jq - ksb[j]));
+                    ladd(aSC, Td * rr[j]);
+                }
             } else {
                 for (int q = 0; q < jend; ++q) {
                     const int j = j0 + q;
