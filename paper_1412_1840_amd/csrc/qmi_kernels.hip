@@ -698,7 +698,8 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
             } else if (nrows == ROWS && j0 >= base + PASS / 2) {
                 // The upper half of the diagonal block: every column pairs with all of the
                 // wave's rows below base + PASS / 2 (the first half, a straight-line body) and
-                // with the first cnt - ROWS / 2 of the others (masked in groups as below).
+                // with the first cnt - ROWS / 2 of the others (masked in groups as below).  The
+                // same terms in the same order as the general masked loop, so the same bits.
                 constexpr int HALF = ROWS / 2;
                 for (int q = 0; q < jend; ++q) {
                     const int j = j0 + q;
