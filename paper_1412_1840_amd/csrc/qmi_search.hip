@@ -17,6 +17,7 @@ namespace {
 // --------------------------------------------------------------------------------------------
 
 constexpr int kPeakBlock = 256;
+constexpr int kPeakBlockWide = 512;
 
 __device__ __forceinline__ bool better(double qa, int ka, double qb, int kb) {
     // a ranks before b: higher score, ties to lower index.  NaN never ranks.
@@ -62,14 +63,15 @@ __device__ __forceinline__ int block_best(double q, int k, double (*wq)[NW], int
     return bk;
 }
 
-__global__ void __launch_bounds__(kPeakBlock)
+template <int BLOCK>
+__global__ void __launch_bounds__(BLOCK)
 peaks_kernel(const CurveParams* __restrict__ cp, const double* __restrict__ coarse, int F,
              double f0, double df, int top_k, int n_fine, MaskDev md, PeakOut po) {
-    constexpr int NW = kPeakBlock / 64;
+    constexpr int NW = BLOCK / 64;
     __shared__ double wq[2][NW];
     __shared__ int wk[2][NW];
     __shared__ int chosen[64];
-    extern __shared__ double peak_dyn[];  // [max(top_k, 1)][kPeakBlock] scores, then indices
+    extern __shared__ double peak_dyn[];  // [max(top_k, 1)][BLOCK] scores, then indices
     const int c = blockIdx.x;
     const double* q = coarse + (int64_t)c * F;
     const bool ok = cp[c].status == 0;
@@ -79,29 +81,29 @@ peaks_kernel(const CurveParams* __restrict__ cp, const double* __restrict__ coar
     // kUnroll grid points per step with their loads issued together.
     constexpr int kUnroll = 4;
     const int TK = top_k > 0 ? top_k : 1;
-    // Entry i of a thread's list sits at i * kPeakBlock + thread (consecutive threads in
+    // Entry i of a thread's list sits at i * BLOCK + thread (consecutive threads in
     // consecutive slots, so that the list operations of a wave do not conflict on LDS banks).
     double* mv0 = reinterpret_cast<double*>(peak_dyn) + threadIdx.x;
-    int* mk0 = reinterpret_cast<int*>(reinterpret_cast<double*>(peak_dyn) + kPeakBlock * TK) +
+    int* mk0 = reinterpret_cast<int*>(reinterpret_cast<double*>(peak_dyn) + BLOCK * TK) +
                threadIdx.x;
-    auto mv = [&](int i) -> double& { return mv0[i * kPeakBlock]; };
-    auto mk = [&](int i) -> int& { return mk0[i * kPeakBlock]; };
+    auto mv = [&](int i) -> double& { return mv0[i * BLOCK]; };
+    auto mk = [&](int i) -> int& { return mk0[i * BLOCK]; };
     int n_loc = 0;
     double bq = NAN;
     int bk = 0x7fffffff;
     if (ok) {
-        for (int k0 = threadIdx.x; k0 < F; k0 += kUnroll * kPeakBlock) {
+        for (int k0 = threadIdx.x; k0 < F; k0 += kUnroll * BLOCK) {
             double v[kUnroll], lft[kUnroll], rgt[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                const int k = k0 + u * kPeakBlock;
+                const int k = k0 + u * BLOCK;
                 v[u] = k < F ? q[k] : NAN;
                 lft[u] = (k < F && k > 0) ? q[k - 1] : NAN;
                 rgt[u] = (k + 1 < F) ? q[k + 1] : NAN;
             }
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                const int k = k0 + u * kPeakBlock;
+                const int k = k0 + u * BLOCK;
                 if (k >= F) break;
                 if (better(v[u], k, bq, bk) && !in_mask(md, grid_f(f0, df, k), v[u])) {
                     bq = v[u];
@@ -252,10 +254,18 @@ hipError_t launch_peaks(hipStream_t st, const CurveParams* cp, int n_curves, con
                         int n_coarse, double f0, double df, int top_k, int n_fine,
                         const MaskDev& md, const PeakOut& po) {
     if (n_curves <= 0) return hipSuccess;
-    const size_t lds =
-        (size_t)kPeakBlock * (top_k > 0 ? top_k : 1) * (sizeof(double) + sizeof(int));
-    peaks_kernel<<<n_curves, kPeakBlock, lds, st>>>(cp, coarse, n_coarse, f0, df, top_k, n_fine,
-                                                     md, po);
+    // A launch of few curves (single-curve calls, serving batches) is one block per curve on a
+    // mostly idle chip: wider blocks there scan the grid in fewer steps, while their per-thread
+    // peak lists still fit the default 64 KiB of dynamic LDS.
+    const int tk = top_k > 0 ? top_k : 1;
+    const size_t per_thread = (size_t)tk * (sizeof(double) + sizeof(int));
+    if (n_curves < 128 && (size_t)kPeakBlockWide * per_thread <= 64 * 1024) {
+        peaks_kernel<kPeakBlockWide><<<n_curves, kPeakBlockWide, kPeakBlockWide * per_thread,
+                                       st>>>(cp, coarse, n_coarse, f0, df, top_k, n_fine, md, po);
+    } else {
+        peaks_kernel<kPeakBlock><<<n_curves, kPeakBlock, kPeakBlock * per_thread, st>>>(
+            cp, coarse, n_coarse, f0, df, top_k, n_fine, md, po);
+    }
     return hipGetLastError();
 }
 
