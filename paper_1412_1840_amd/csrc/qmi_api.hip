@@ -674,8 +674,26 @@ int run_group(qmi_ctx* ctx, const qmi_batch* b, const CallSpec& cs, const Group&
         {
             PairOut pc1 = po;
             pc1.part = split1 ? dpart : nullptr;
-            HIP_OK(ctx, launch_pairs<R>(st, dcp, dorder, nc, fp, t, K, rd, rp, ks, pc1, variant,
+            // Per-curve lists whose last tile would hold only one or two slots (the bands
+            // method's 450 trials): the main launch stops before that tile, and a kernel with one
+            // row per lane takes its slots (FP32 path).
+            FreqPlan fpm = fp;
+            int rem_slot0 = -1;
+            if constexpr (sizeof(R) == 4) {
+                const int full = fp.count / kLanes, rem = fp.count % kLanes;
+                if (fp.kind == 3 && variant != kVariantFold32 && full > 0 && rem > 0 &&
+                    rem <= kRemSlots) {
+                    fpm.tile_cap = full;
+                    rem_slot0 = full * kLanes;
+                }
+            }
+            HIP_OK(ctx, launch_pairs<R>(st, dcp, dorder, nc, fpm, t, K, rd, rp, ks, pc1, variant,
                                         split1 ? max_pieces : 0));
+            if constexpr (sizeof(R) == 4) {
+                if (rem_slot0 >= 0)
+                    HIP_OK(ctx, launch_pairs_rows(st, dcp, dorder, nc, fp, rem_slot0, t, K, rd,
+                                                  pc1));
+            }
         }
         rec();
         if (bp) {

@@ -83,7 +83,7 @@ struct FreqPlan {
     int32_t n_fine;
     int32_t top_k;
     int32_t stride;  // kind 3: row length of the per-curve lists
-    int32_t pad;
+    int32_t tile_cap;  // > 0: the pair kernel runs only the first tile_cap tiles of kLanes slots
     double f0, df;           // kind 0: f = f0 + s * df
     const double* list;      // kind 1: [count]; kind 3: [curve][stride], NaN = no frequency
     const double* win;       // kind 2: [curve][top_k][2] = (lo, step)
@@ -202,6 +202,12 @@ hipError_t launch_pairs(hipStream_t st, const CurveParams* cp, const int32_t* or
                         int n_work_curves, const FreqPlan& fp, const double* t, const R* K,
                         const double* rd, const double* rp, const R* ks, const PairOut& out,
                         int variant, int split_pmax);
+// The last kRemSlots slots of per-curve frequency lists (fp.kind 3) from slot0 on, one row per
+// lane (FP32 path; pairs with fp.tile_cap = slot0 / kLanes on the main launch).
+constexpr int kRemSlots = kLanes / 32;
+hipError_t launch_pairs_rows(hipStream_t st, const CurveParams* cp, const int32_t* order,
+                             int n_work_curves, const FreqPlan& fp, int slot0, const double* t,
+                             const float* K, const double* rd, const PairOut& out);
 hipError_t launch_peaks(hipStream_t st, const CurveParams* cp, int n_curves, const double* coarse,
                         int n_coarse, double f0, double df, int top_k, int n_fine,
                         const MaskDev& md, const PeakOut& po);

@@ -506,7 +506,7 @@ pairs_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ ord
 
     const int lane = threadIdx.x & 63;
     const int w = uniform((int)(threadIdx.x >> 6));
-    const int tiles = (fp.count + kLanes - 1) / kLanes;
+    const int tiles = fp.tile_cap > 0 ? fp.tile_cap : (fp.count + kLanes - 1) / kLanes;
     // The dispatcher deals blocks to the XCDs round robin (block b runs on XCD b mod kXcds), and
     // each XCD has its own L2.  With enough curves (xcd_grouped), every XCD gets whole curves
     // (work ranks x, x + kXcds, ...) with their frequency tiles in consecutive blocks, so that a
@@ -847,6 +847,7 @@ pair_epilogue_kernel(const CurveParams* __restrict__ cp, const int32_t* __restri
     const int64_t rank = idx / fp.count;
     if (rank >= n_work) return;
     const int slot = (int)(idx - rank * fp.count);
+    if (fp.tile_cap > 0 && slot >= fp.tile_cap * kLanes) return;  // another launch's slots
     const int c = order[rank];
     const CurveParams P = cp[c];
     bool active;
@@ -873,6 +874,128 @@ pair_epilogue_kernel(const CurveParams* __restrict__ cp, const int32_t* __restri
         SC += pp[2];
     }
     pair_scores(P, SJ, ST, SC, obase, out);
+}
+
+// The last, nearly empty tile of per-curve frequency lists (the bands method's 3 x 150 trials
+// leave 2 slots in a curve's eighth tile of 64): in pairs_kernel its 2 active lanes would cost a
+// whole tile.  Here a workgroup takes the curve's last kRemSlots slots with lanes = (slot,
+// row): lane l holds slot slot0 + l / 32 and row base + w + kWaves (l mod 32) of each pass, the
+// interleaved rows of pairs_kernel, and every lane walks the pass's columns j > base through LDS.
+// Per pair (i, j), i < j: g_ij from the same warp vectors and exp as pairs_kernel; the lane adds g
+// (its row's part of S_T and, times the FP64 r_i, of S_C), r_j g (the column part of S_C) and
+// K(i, j) (g - 1) (S_J, exactly zero where g = 1), in FP32 runs of kRowFold columns folded into
+// FP64.  The 32 row lanes of a slot and the waves are then added in a fixed order.  FP32 path only
+// (the FP64 and FP32-fold instances keep the plain tiles).
+__global__ void __launch_bounds__(kThreads, 2)
+pairs_rows_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ order,
+                  FreqPlan fp, int slot0, const double* __restrict__ t_all,
+                  const float* __restrict__ K_all, const double* __restrict__ rd_all, int n_work,
+                  PairOut out) {
+    using W = Warp<float, false>;
+    using V = W::V;
+    constexpr int ROWS = rows_per_wave<float>();
+    constexpr int PASS = kWaves * ROWS;
+    constexpr int CH = kChunk;
+    constexpr int kFold = 64;  // columns per FP32 run
+    static_assert(ROWS * kRemSlots == kLanes, "one row per lane and slot");
+    __shared__ V ph[CH][kLanes];
+    __shared__ double fq[kLanes];
+    __shared__ double red[3][kWaves][kRemSlots];
+
+    const int lane = threadIdx.x & 63;
+    const int w = uniform((int)(threadIdx.x >> 6));
+    const int rank = (int)blockIdx.x;
+    if (rank >= n_work) return;
+    const int c = order[rank];
+    const CurveParams P = cp[c];
+    const int half = lane / ROWS, r = lane % ROWS;
+    bool active;
+    const double f = slot_freq(fp, c, slot0 + half, active);
+    const int64_t obase = (int64_t)c * fp.count + slot0 + half;
+    if (P.status != 0) {
+        if (active && w == 0 && r == 0) {
+            out.score[obase] = NAN;
+            if (out.score2) out.score2[obase] = NAN;
+            if (out.ips) {
+                out.ips[obase * 3 + 0] = NAN;
+                out.ips[obase * 3 + 1] = NAN;
+                out.ips[obase * 3 + 2] = NAN;
+            }
+        }
+        return;
+    }
+    const int n = P.n;
+    const double* t = t_all + P.off;
+    const double* rr = rd_all + P.off;
+    const double scale = uniform(sqrt(sqrt(2.0 * kLog2e) / P.sigma_t));
+    if (w == 0) fq[lane] = f;
+    __syncthreads();
+
+    double SJ = 0.0, ST = 0.0, SC = 0.0;
+    for (int base = 0; base < n; base += PASS) {
+        const int i = base + w + kWaves * r;  // this lane's row
+        const bool has_row = i < n;
+        const V ui = has_row ? W::at(fq[lane], t[i], scale) : V{0.f, 0.f};
+        const double ri = has_row ? rr[i] : 0.0;
+        // K(i, j) for this lane's row: column j's run of the wave's rows, element r.
+        const float* kc = K_all + P.koff + kperm(base + w) + r;
+        float gs = 0.f, cs = 0.f, js = 0.f;
+        int run = 0;
+        for (int j0 = base; j0 < n; j0 += CH) {
+            __syncthreads();  // the previous chunk's columns have been read
+            for (int q = w; q < CH; q += kWaves) {
+                const int j = j0 + q;
+                const int ls = fresh_lane();
+                ph[q][ls] = (j < n) ? W::at(fq[ls], t[j], scale) : V{0.f, 0.f};
+            }
+            __syncthreads();
+            const int jend = min(CH, n - j0);
+            for (int q = 0; q < jend; ++q) {
+                const int j = j0 + q;
+                const V u = ph[q][lane];
+                const bool pair = has_row && i < j;
+                const float k = pair ? kc[(int64_t)j * P.npad] : 0.f;
+                const float rj = (float)rr[j];
+                const float pr = ui.x * u.y;
+                const float d = fmaf(ui.y, u.x, -pr);
+                const float a = fmaf(d, d, pair ? 0.f : INFINITY);
+                const float g = W::kexp(-a);
+                gs += g;
+                cs = fmaf(rj, g, cs);
+                js = fmaf(k, g - 1.f, js);
+                if (++run == kFold) {
+                    ST += (double)gs;
+                    SC = fma((double)gs, ri, SC + (double)cs);
+                    SJ += (double)js;
+                    gs = cs = js = 0.f;
+                    run = 0;
+                }
+            }
+        }
+        ST += (double)gs;
+        SC = fma((double)gs, ri, SC + (double)cs);
+        SJ += (double)js;
+    }
+    // The 32 row lanes of each slot (butterfly within the half-wave), then the waves in order.
+    for (int o = ROWS / 2; o > 0; o >>= 1) {
+        SJ += __shfl_xor(SJ, o, 64);
+        ST += __shfl_xor(ST, o, 64);
+        SC += __shfl_xor(SC, o, 64);
+    }
+    if (r == 0) {
+        red[0][w][half] = SJ;
+        red[1][w][half] = ST;
+        red[2][w][half] = SC;
+    }
+    __syncthreads();
+    if (w != 0 || r != 0 || !active) return;
+    double sj = 0.0, st = 0.0, sc = 0.0;
+    for (int v = 0; v < kWaves; ++v) {
+        sj += red[0][v][half];
+        st += red[1][v][half];
+        sc += red[2][v][half];
+    }
+    pair_scores(P, sj, st, sc, obase, out);
 }
 
 }  // namespace
@@ -1007,7 +1130,7 @@ hipError_t launch_pairs(hipStream_t st, const CurveParams* cp, const int32_t* or
                         const double* r, const double* rp, const R* ks, const PairOut& out,
                         int variant, int split_pmax) {
     if (n_work_curves <= 0 || fp.count <= 0) return hipSuccess;
-    const int64_t tiles = (fp.count + kLanes - 1) / kLanes;
+    const int64_t tiles = fp.tile_cap > 0 ? fp.tile_cap : (fp.count + kLanes - 1) / kLanes;
     PairGrid g;
     g.n_work = n_work_curves;
     if (split_pmax > 0 && out.part) {
@@ -1032,6 +1155,15 @@ hipError_t launch_pairs(hipStream_t st, const CurveParams* cp, const int32_t* or
     g.blocks = (unsigned)(rows * tiles);
     return launch_pairs_grid<R>(st, cp, order, g, fp, t, K, r, rp, ks, out, variant);
 }
+hipError_t launch_pairs_rows(hipStream_t st, const CurveParams* cp, const int32_t* order,
+                             int n_work_curves, const FreqPlan& fp, int slot0, const double* t,
+                             const float* K, const double* rd, const PairOut& out) {
+    if (n_work_curves <= 0 || slot0 >= fp.count) return hipSuccess;
+    pairs_rows_kernel<<<(unsigned)n_work_curves, kThreads, 0, st>>>(cp, order, fp, slot0, t, K,
+                                                                     rd, n_work_curves, out);
+    return hipGetLastError();
+}
+
 template hipError_t launch_pairs<float>(hipStream_t, const CurveParams*, const int32_t*, int,
                                         const FreqPlan&, const double*, const float*,
                                         const double*, const double*, const float*,
