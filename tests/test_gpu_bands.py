@@ -109,6 +109,33 @@ def test_trials_and_best_match_oracle(ctx, n_grid):
                                                         / (grid[1] - grid[0])))
 
 
+@pytest.mark.parametrize("n_keep,n_trials", [(1, 129), (3, 150), (2, 33)])
+def test_last_tile_scores_match_oracle(ctx, n_keep, n_trials):
+    """Trial lists of n_keep * n_trials slots: 129 and 450 slots end in a tile of 1 or 2 slots
+    (taken by the one-row-per-lane kernel), 66 in a tile of 2 after one full tile.  Every scored
+    trial, the last ones included, against the oracle's score of the same frequency."""
+    curves = [synth.survey_batch_curve(200 + k, n=n) for k, n in
+              enumerate([5, 40, 255, 256, 257, 300, 511, 700, 1024])]
+    b = synth.pack(curves)
+    res, trials, scores = ctx.bands_best_period(b.offsets, b.t, b.y, b.e, 0.3, n_keep=n_keep,
+                                                n_trials=n_trials)
+    assert trials.shape == (len(curves), n_keep * n_trials)
+    for k, c in enumerate(curves):
+        assert res[k]["status"] == 0
+        ok = ~np.isnan(trials[k])
+        assert np.all(np.isnan(scores[k][~ok]))
+        q = O.qmi(O.information_potentials(c.t, c.y, 0.3, O.silverman_sigma(c.y),
+                                           trials[k][ok]))
+        den = np.maximum(np.abs(q), 1e-3 * np.max(np.abs(q)))
+        assert np.max(np.abs(scores[k][ok] - q) / den) <= QMI_TOL, (k, c.n)
+        last = np.flatnonzero(ok)
+        last = last[last >= (n_keep * n_trials // 64) * 64]
+        if len(last):
+            lq = q[np.searchsorted(np.flatnonzero(ok), last)]
+            ld = np.maximum(np.abs(lq), 1e-3 * np.max(np.abs(q)))
+            assert np.max(np.abs(scores[k][last] - lq) / ld) <= QMI_TOL, (k, c.n, last)
+
+
 def test_bands_status_and_argument_errors(ctx):
     good = synth.survey_batch_curve(1, n=200)
     bad = synth.survey_batch_curve(2, n=50)
