@@ -880,11 +880,10 @@ pair_epilogue_kernel(const CurveParams* __restrict__ cp, const int32_t* __restri
 // leave 2 slots in a curve's eighth tile of 64): in pairs_kernel its 2 active lanes would cost a
 // whole tile.  Here a workgroup takes the curve's last kRemSlots slots with lanes = (slot,
 // row): lane l holds slot slot0 + l / 32 and row base + w + kWaves (l mod 32) of each pass, the
-// interleaved rows of pairs_kernel, and every lane walks the pass's columns j > base through LDS.
+// interleaved rows of pairs_kernel, and every lane walks the pass's columns j >= base through LDS.
 // Per pair (i, j), i < j: g_ij from the same warp vectors and exp as pairs_kernel; the lane adds g
 // (its row's part of S_T and, times the FP64 r_i, of S_C), r_j g (the column part of S_C) and
-// K(i, j) (g - 1) (S_J, exactly zero where g = 1), in FP32 runs of kRowFold columns folded into
-// FP64.  The 32 row lanes of a slot and the waves are then added in a fixed order.  FP32 path only
+// K(i, j) (g - 1) (S_J, exactly zero where g = 1), in FP32 runs of 64 columns folded into FP64.  The 32 row lanes of a slot and the waves are then added in a fixed order.  FP32 path only
 // (the FP64 and FP32-fold instances keep the plain tiles).
 __global__ void __launch_bounds__(kThreads, 2)
 pairs_rows_kernel(const CurveParams* __restrict__ cp, const int32_t* __restrict__ order,
